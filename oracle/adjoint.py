@@ -1,0 +1,124 @@
+"""Implicit differentiation of a converged V-FPI step (float64, test infrastructure).
+
+The V-FPI map of the paper's convergence analysis (Sec. IV, Lemma 1 framing)
+is f(v) = v* + W J_c^T lambda(v*), v* = v - W (A v - b),
+lambda = P(-Gamma^{-1}(J_c v* + phi e1); mu) with P the strict projection
+(eq. operator, Alg. 2).  At its fixed point the solution is independent of W
+(consistency remark, Sec. III-B), so W is held constant.  Linearizing with
+D_P the 3x3 Jacobian of P per contact (branch of the last projection:
+open 0; stick I; slip dl_n/dn = 1, dl_t/dn = mu t/s, dl_t/dt = (mu n/s)(I - t t^T/s^2),
+dl_t/dmu = n t/s, with (n, t) = lambda*, s = ||t||) and
+
+    G = I - W J^T D_P Gamma^{-1} J
+
+the adjoint u of a loss with gradients (g_v, g_lam) solves
+
+    u = g~ + (I - A W) G^T u,        g~ = g_v - (I - A W) J^T Gamma^{-1} D_P^T g_lam
+
+and then, with r = J W u + g_lam and q = u - J^T Gamma^{-1} D_P^T r:
+
+    b_bar = W q,   A_bar_ij = -b_bar_i v_j (on the pattern of A),
+    phi_bar_m = -(D_P,m^T r_m)_n / gamma_m,   mu_bar_m = (dP_m/dmu)^T r_m.
+
+``adjoint`` solves for u by the transposed fixed-point iteration (SciPy
+matvecs); ``adjoint_dense`` solves the same linear system with a dense LU.
+Pins: the two agree; gradients match central finite differences of the
+oracle's converged forward; they are the same for two different W; and the
+sliding particle's closed form dx_N/dmu = -h^2 g cos(a) N(N+1)/2.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .core import BRANCH_SLIP, BRANCH_STICK, contact_jacobian, system_matrix
+
+
+def projection_jacobians(lam_star, branch, mu):
+    """Per contact: D_P [nc,3,3] and dP/dmu [nc,3]."""
+    nc = lam_star.shape[0]
+    DP = np.zeros((nc, 3, 3))
+    dmu = np.zeros((nc, 3))
+    st = branch == BRANCH_STICK
+    DP[st] = np.eye(3)
+    sl = np.nonzero(branch == BRANCH_SLIP)[0]
+    if sl.size:
+        n = lam_star[sl, 0]
+        t = lam_star[sl, 1:]
+        s = np.linalg.norm(t, axis=1)
+        th = t / s[:, None]
+        m = mu[sl]
+        DP[sl, 0, 0] = 1.0
+        DP[sl, 1:, 0] = m[:, None] * th
+        DP[sl, 1:, 1:] = (m * n / s)[:, None, None] * (np.eye(2) - th[:, :, None] * th[:, None, :])
+        dmu[sl, 1:] = n[:, None] * th
+    return DP, dmu
+
+
+def _operators(p, fwd):
+    A = system_matrix(p)
+    J = contact_jacobian(p)
+    DP, dmu = projection_jacobians(fwd["lam_star"], fwd["branch"], p.mu)
+    DPb = sp.block_diag(list(DP), format="csr") if p.n_contacts else sp.csr_matrix((0, 0))
+    ginv = np.repeat(1.0 / fwd["gamma"], 3)
+    return A, J, DP, dmu, DPb, ginv
+
+
+def _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv):
+    w = fwd["w"]
+    nc = p.n_contacts
+    r = J @ (w * u) + g_lam
+    q = u - J.T @ (ginv * (DPb.T @ r))
+    b_bar = w * q
+    rm = r.reshape(nc, 3)
+    dpr = np.einsum("mji,mj->mi", DP, rm)           # D_P^T r per contact
+    phi_bar = -dpr[:, 0] / fwd["gamma"]
+    mu_bar = np.einsum("mi,mi->m", dmu, rm)
+    # A_bar on the block pattern: block (i, c) = -b_bar_i v_c^T
+    rows = np.repeat(np.arange(p.n_nodes), np.diff(p.row_ptr))
+    A_bar = -b_bar.reshape(-1, 3)[rows][:, :, None] * fwd["v"].reshape(-1, 3)[p.col_idx][:, None, :]
+    return {"u": u, "b": b_bar, "A": A_bar, "phi": phi_bar, "mu": mu_bar}
+
+
+def adjoint(p, fwd, g_v, g_lam=None, *, tol=1e-14, max_iters=100000):
+    A, J, DP, dmu, DPb, ginv = _operators(p, fwd)
+    w = fwd["w"]
+    nc = p.n_contacts
+    g_lam = np.zeros(3 * nc) if g_lam is None else np.asarray(g_lam, dtype=np.float64).ravel()
+
+    def i_minus_aw(x):
+        return x - A @ (w * x)
+
+    def gt(x):  # G^T x
+        return x - J.T @ (ginv * (DPb.T @ (J @ (w * x))))
+
+    g_t = g_v - i_minus_aw(J.T @ (ginv * (DPb.T @ g_lam)))
+    u = g_t.copy()
+    it = 0
+    theta = np.inf
+    for it in range(1, max_iters + 1):
+        u_new = g_t + i_minus_aw(gt(u))
+        theta = float(np.linalg.norm(u_new - u))
+        u = u_new
+        if theta < tol:
+            break
+    out = _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv)
+    out.update(iters=it, theta=theta)
+    return out
+
+
+def adjoint_dense(p, fwd, g_v, g_lam=None):
+    A, J, DP, dmu, DPb, ginv = _operators(p, fwd)
+    w = fwd["w"]
+    n, nc = p.n, p.n_contacts
+    g_lam = np.zeros(3 * nc) if g_lam is None else np.asarray(g_lam, dtype=np.float64).ravel()
+    Ad = A.toarray()
+    W = np.diag(w)
+    Jd = J.toarray()
+    Gam_inv = np.diag(ginv)
+    DPd = DPb.toarray() if nc else np.zeros((0, 0))
+    G = np.eye(n) - W @ Jd.T @ DPd @ Gam_inv @ Jd
+    IAW = np.eye(n) - Ad @ W
+    g_t = g_v - IAW @ (Jd.T @ (Gam_inv @ (DPd.T @ g_lam)))
+    u = np.linalg.solve(np.eye(n) - IAW @ G.T, g_t)
+    return _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv)

@@ -1,0 +1,123 @@
+"""Pins of the oracle adjoint of a converged V-FPI step: the transposed
+fixed-point solve against a dense LU, central finite differences of the
+converged forward, W-independence, and the sliding particle's closed form."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle.adjoint import adjoint, adjoint_dense
+
+
+def _fwd(p, **kw):
+    kw.setdefault("max_iters", 200000)
+    kw.setdefault("tol", 1e-15)
+    return oracle.vfpi(p, **kw)
+
+
+def _problem(seed):
+    return scenes.random_problem(14, 7, seed, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_iterative_adjoint_matches_dense(seed):
+    p = _problem(seed)
+    f = _fwd(p)
+    g = np.random.default_rng(seed)
+    gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+    a = adjoint(p, f, gv, gl)
+    d = adjoint_dense(p, f, gv, gl)
+    for k in ("b", "A", "phi", "mu"):
+        np.testing.assert_allclose(a[k], d[k], rtol=0, atol=1e-10 * (1 + np.abs(d[k]).max()))
+
+
+def _loss(p, gv, gl):
+    f = _fwd(p)
+    return gv @ f["v"] + gl @ f["lam"].ravel(), f["branch"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_adjoint_matches_central_differences(seed):
+    p = _problem(seed)
+    f = _fwd(p)
+    g = np.random.default_rng(100 + seed)
+    gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+    grad = adjoint(p, f, gv, gl)
+    eps = 1e-6
+    checked = 0
+
+    def fd(make):
+        lp, bp = _loss(make(+eps), gv, gl)
+        lm, bm = _loss(make(-eps), gv, gl)
+        if not (np.array_equal(bp, f["branch"]) and np.array_equal(bm, f["branch"])):
+            return None  # the active set changed inside +-eps: not differentiable there
+        return (lp - lm) / (2 * eps)
+
+    def with_(name, arr):
+        return scenes.Problem(**{**p.__dict__, name: arr})
+
+    for k in g.choice(p.n, 6, replace=False):
+        e = np.zeros(p.n)
+        e[k] = 1
+        val = fd(lambda s: with_("b", p.b + s * e))
+        if val is not None:
+            assert abs(val - grad["b"][k]) <= 1e-6 * (1 + abs(val))
+            checked += 1
+    for m in range(p.n_contacts):
+        e = np.zeros(p.n_contacts)
+        e[m] = 1
+        for name in ("phi", "mu"):
+            val = fd(lambda s: with_(name, getattr(p, name) + s * e))
+            if val is not None:
+                assert abs(val - grad[name][m]) <= 1e-6 * (1 + abs(val)), (name, m)
+                checked += 1
+    # symmetric perturbation of one off-diagonal block pair of A
+    rows = np.repeat(np.arange(p.n_nodes), np.diff(p.row_ptr))
+    offd = np.nonzero(rows != p.col_idx)[0]
+    for blk in g.choice(offd, 3, replace=False):
+        i, c = rows[blk], p.col_idx[blk]
+        tr = p.row_ptr[c] + np.nonzero(p.col_idx[p.row_ptr[c]:p.row_ptr[c + 1]] == i)[0][0]
+        E = np.zeros_like(p.val)
+        E[blk, 0, 1] = 1
+        E[tr, 1, 0] = 1
+        val = fd(lambda s: with_("val", p.val + s * E))
+        if val is not None:
+            exp = grad["A"][blk, 0, 1] + grad["A"][tr, 1, 0]
+            assert abs(val - exp) <= 1e-6 * (1 + abs(val))
+            checked += 1
+    assert checked >= 10
+
+
+def test_gradient_independent_of_w():
+    p = _problem(3)
+    g = np.random.default_rng(7)
+    gv = g.normal(size=p.n)
+    f1 = _fwd(p)
+    alpha = oracle.core.gershgorin_alpha(oracle.system_matrix(p))
+    f2 = _fwd(p, w_mode="scalar", alpha_user=alpha)
+    a1, a2 = adjoint(p, f1, gv), adjoint(p, f2, gv)
+    for k in ("b", "phi", "mu"):
+        np.testing.assert_allclose(a1[k], a2[k], atol=1e-8 * (1 + np.abs(a1[k]).max()))
+
+
+def test_sliding_particle_closed_form():
+    """x_N . t = h^2 g (sin a - mu cos a) N (N+1) / 2 for a particle sliding from
+    rest, so dL/dmu = -h^2 g cos(a) N (N+1) / 2 with L = t . x_N."""
+    a, mu, m, h, g, N = 0.5, 0.2, 1.3, 0.01, 9.81, 20
+    t_dir = np.array([np.cos(a), 0.0, -np.sin(a)])
+    v = np.zeros(3)
+    steps = []
+    for _ in range(N):
+        p = scenes.inclined_plane_particles([a], [mu], mass=m, h=h, g=g, v_k=v[None])
+        f = _fwd(p)
+        steps.append((p, f))
+        v = f["v"]
+    # reverse sweep: L = t . x_N, x_k = x_{k-1} + h v_k, b_{k+1} = m (v_k + h g)
+    mu_bar = 0.0
+    v_bar_next_b = np.zeros(3)
+    for p, f in reversed(steps):
+        gv = h * t_dir + m * v_bar_next_b
+        ad = adjoint(p, f, gv)
+        mu_bar += ad["mu"][0]
+        v_bar_next_b = ad["b"]
+    np.testing.assert_allclose(mu_bar, -h * h * g * np.cos(a) * N * (N + 1) / 2, rtol=1e-10)
