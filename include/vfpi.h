@@ -1,0 +1,201 @@
+/*
+ * vfpi.h -- C ABI of the V-FPI contact solver for AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Large-Dimensional Multibody Dynamics Simulation Using Contact
+ * Nodalization and Diagonalization" (J. Lee, M. Lee, D. Lee).  One time step
+ * solves the linear contact problem
+ *
+ *     A v = b + J_c^T lambda,  Signorini-Coulomb complementarity per contact
+ *                                              (Sec. II, eq. lindyn, eq. scc)
+ *
+ * with the velocity fixed-point iteration (V-FPI, Alg. 1): each sweep is
+ *     v*      = v^l - W (A v^l - b)                           (eq. pgd1)
+ *     eta_m   = R_m v*_i                                      (eq. subp, nodal J_c)
+ *     lambda_m = ProjectFC(-(eta_m + phi_m e1) / gamma_m)     (Alg. 2, eq. operator)
+ *     v^{l+1} = v* + W J_c^T lambda                           (eq. vup)
+ *     theta   = ||v^{l+1} - v^l||_2,  stop if theta < tol or l = max_iters
+ * where W is diagonal with one shared value w_i on the three DOFs of every
+ * contact node, so that J_c W J_c^T = diag(gamma_m I3) with gamma_m = w_i
+ * (Prop. 3, eq. diagonal).
+ *
+ * Conventions for every entry point:
+ *  - All array pointers are DEVICE pointers owned by the caller, except the
+ *    descriptor structs themselves (host memory, read during the call only).
+ *  - Work is enqueued asynchronously on `stream`; results (outputs and the
+ *    device-side stats record) are valid once the stream has synchronized.
+ *  - Inputs are never modified.  `v` is in/out (warm start in, solution out);
+ *    every other output is fully overwritten.
+ *  - Sizes: N nodes, n = 3N DOFs, node-major vectors (x,y,z of node 0, ...).
+ *    Indices are int32.
+ *  - Synchronous argument errors return a negative VFPI_E_* code and enqueue
+ *    nothing.  Data errors that need the device to detect are reported in
+ *    stats->status (VFPI_S_* bits); when any is set the solve is skipped:
+ *    v is left as given, lambda is zeroed, iters = 0.
+ *  - A context owns device workspace sized at creation; one context must not
+ *    be used by two streams at once (calls on one stream are ordered).
+ */
+#ifndef VFPI_H
+#define VFPI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes (synchronous) ---------------------------------------- */
+#define VFPI_OK              0
+#define VFPI_E_NULL         -1  /* a required pointer is NULL                  */
+#define VFPI_E_SHAPE        -2  /* inconsistent sizes (negative, n_c > N, ...)  */
+#define VFPI_E_OPTS         -3  /* invalid option value                         */
+#define VFPI_E_CAPACITY     -4  /* larger than the context was created for     */
+#define VFPI_E_UNSUPPORTED  -5  /* valid input this build does not solve       */
+#define VFPI_E_HIP          -6  /* a HIP runtime call failed                    */
+#define VFPI_E_NO_TAPE      -7  /* backward without a forward tape              */
+
+/* ---- device status (stats.status) -------------------------------------- */
+#define VFPI_S_CONVERGED        0x000  /* theta < tol at the break            */
+#define VFPI_S_MAXITER          0x001  /* stopped at max_iters (or fixed_iters) */
+#define VFPI_S_NONFINITE        0x010  /* NaN/Inf in A, b, v, R, phi or mu     */
+#define VFPI_S_NOT_NODAL        0x020  /* J_c row is not one block (S-contact) */
+#define VFPI_S_NOT_ORTHONORMAL  0x040  /* max |R R^T - I| > 1e-10 (1e-5 in FP32) */
+#define VFPI_S_SHARED_NODE      0x080  /* a node carries two contacts (Prop. 3)  */
+#define VFPI_S_NONPOS_DIAG      0x100  /* a_ii <= 0 or no diagonal block        */
+#define VFPI_S_BAD_PATTERN      0x200  /* column index out of range / out of env */
+#define VFPI_S_BAD_W            0x400  /* user W not positive, or unequal on a contact node */
+#define VFPI_S_BAD_MU           0x800  /* mu < 0                               */
+
+/* ---- step-size matrix W (Sec. IV-C) ------------------------------------ */
+#define VFPI_W_FROBENIUS    0  /* w_d = a_dd/||A_d*||^2, shared on contact nodes (Sec. IV-C.1) */
+#define VFPI_W_USER_DIAG    1  /* opts.w_user[n], equal on the 3 DOFs of each contact node */
+#define VFPI_W_USER_SCALAR  2  /* W = opts.alpha_user I                        */
+#define VFPI_W_BB1          3  /* Barzilai-Borwein s's/s'z (Sec. IV-C.2)       */
+#define VFPI_W_BB2          4  /* Barzilai-Borwein s'z/z'z (Sec. IV-C.2)       */
+
+/* ---- ProjectFC (eq. operator) ------------------------------------------ */
+#define VFPI_PROJ_STRICT    0  /* normal clamp + disk projection (default)     */
+#define VFPI_PROJ_PROXIMAL  1  /* Euclidean projection onto the friction cone  */
+
+/* Block-sparse row matrix with 3x3 blocks (the system matrix A_k, eq. akbk).
+ * row_ptr[n_nodes+1], col_idx[nnzb] (node indices), val[9*nnzb] row-major
+ * blocks, double (vfpi_step, vfpi_step_backward) or float (vfpi_step_batched).
+ * A must be symmetric positive definite with a diagonal block in every row;
+ * symmetry is the caller's promise (it is not checked). */
+typedef struct {
+  int32_t n_nodes;
+  int32_t nnzb;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+} vfpi_bsr;
+
+/* Nodal contact Jacobian J_c (eq. jcnode) in the same block-row form, one
+ * block row per contact: this build solves S-contacts, i.e. rows holding one
+ * block R_m in SO(3) (row 0 = contact normal, rows 1-2 = tangents) at the
+ * contact's node.  phi[n_contacts] is the normal offset term and
+ * mu[n_contacts] >= 0 the friction coefficient (eq. scc).  At most one
+ * contact per node.  Element type as for vfpi_bsr.val. */
+typedef struct {
+  int32_t n_contacts;
+  int32_t nnzb;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+  const void* phi;
+  const void* mu;
+} vfpi_contacts;
+
+typedef struct {
+  int32_t max_iters;     /* l_max of Alg. 1 (>= 0)                             */
+  int32_t fixed_iters;   /* 1: ignore tol, run exactly max_iters sweeps         */
+  double  tol;           /* theta_th of Alg. 1, absolute (m/s)                  */
+  int32_t w_mode;        /* VFPI_W_*                                            */
+  int32_t projection;    /* VFPI_PROJ_*                                         */
+  const void* w_user;    /* device [n], VFPI_W_USER_DIAG only                   */
+  double  alpha_user;    /* VFPI_W_USER_SCALAR only                             */
+  int32_t reuse_w;       /* 1: keep the row sums a_dd, ||A_d*||^2 of the previous
+                            call on this context (W reuse across steps, Sec. IV-C) */
+  int32_t variant;       /* kernel variant, 0 = library default (autotuned)     */
+} vfpi_opts;
+
+/* Written on the device; `stats` points to device memory. */
+typedef struct {
+  int32_t iters;         /* sweeps executed (l at the break)                   */
+  int32_t status;        /* VFPI_S_*                                           */
+  double  theta;         /* residual of the last sweep (+inf if none ran)      */
+  int32_t n_open, n_stick, n_slip;  /* branch counts of the last sweep        */
+  int32_t reserved;
+} vfpi_stats;
+
+/* Create a context able to solve problems up to the given sizes.
+ * max_envs bounds vfpi_step_batched (0 if unused).  Allocates device memory
+ * on the current device.  Returns VFPI_E_SHAPE for negative sizes,
+ * VFPI_E_HIP if allocation fails (then *ctx is NULL). */
+typedef struct vfpi_ctx vfpi_ctx;
+int vfpi_create(vfpi_ctx** ctx, int32_t max_nodes, int32_t max_nnzb, int32_t max_contacts,
+                int32_t max_envs);
+/* Free a context (NULL is a no-op).  Synchronizes the device first. */
+int vfpi_destroy(vfpi_ctx* ctx);
+
+/* Bytes of the forward tape needed by vfpi_step_backward (w, v, lambda*,
+ * branch per contact).  Host-only arithmetic, no device access. */
+int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts);
+
+/* One plain FP64 V-FPI solve (Alg. 1 inner loop, Alg. 2 contact step).
+ *   A       FP64 system matrix A_k (eq. lindyn)
+ *   b       [n]  right-hand side b_k
+ *   Jc      FP64 nodal contact Jacobian, phi, mu (S-contacts)
+ *   v       [n]  in: warm start v^1 (Sec. V-A.5); out: v^{l+1} of the last sweep
+ *   lambda  [3 n_c] out: contact impulses (n, t1, t2) of the last sweep
+ *   opts    options (host struct)
+ *   stats   device vfpi_stats, written at the end
+ *   tape    NULL, or a device buffer of vfpi_tape_bytes(N, n_c) bytes that
+ *           receives what vfpi_step_backward needs
+ * Errors: VFPI_E_NULL, VFPI_E_SHAPE, VFPI_E_OPTS, VFPI_E_CAPACITY,
+ * VFPI_E_UNSUPPORTED (a J_c row with two blocks: D-contacts), VFPI_E_HIP. */
+int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc,
+              double* v, double* lambda, const vfpi_opts* opts, vfpi_stats* stats,
+              void* tape, hipStream_t stream);
+
+/* Many independent problems ("environments") in one launch, FP32 arithmetic
+ * with the residual theta accumulated and tested in FP64.  The envs are
+ * concatenated block-diagonally: env e owns nodes
+ * [env_node_off[e], env_node_off[e+1]) and contacts [env_con_off[e],
+ * env_con_off[e+1]); A, b, Jc, v, lambda use global node/contact indices and
+ * FP32 values.  env_order (device [n_env] permutation, or NULL) is the order
+ * in which the persistent kernel's work queue hands out envs (largest first is
+ * a good choice).  per_env_stats: device [n_env].  Every option applies to
+ * every env; each env stops on its own theta.  W modes: FROBENIUS,
+ * USER_SCALAR.  Errors as vfpi_step. */
+int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* env_node_off,
+                      const int32_t* env_con_off, const int32_t* env_order,
+                      const vfpi_bsr* A, const float* b, const vfpi_contacts* Jc,
+                      float* v, float* lambda, const vfpi_opts* opts,
+                      vfpi_stats* per_env_stats, hipStream_t stream);
+
+/* Adjoint of a converged vfpi_step (implicit differentiation through the
+ * fixed point, with the strict projection's active branch per contact):
+ * given dL/dv and optionally dL/dlambda of the step's outputs, writes dL/db,
+ * dL/dA (on A's pattern, NULL to skip), dL/dphi and dL/dmu.
+ *   A, Jc     the same matrices as the forward call (FP64)
+ *   tape      the buffer filled by the forward call
+ *   grad_v    [n];  grad_lambda [3 n_c] or NULL (zero)
+ *   grad_b    [n] out; grad_A_val [9 nnzb] out or NULL; grad_phi, grad_mu [n_c] out
+ *   opts      max_iters / tol of the adjoint's own fixed-point iteration
+ * The adjoint u solves u = g + (I - A W) G^T u with G = I - W J^T D_P Gamma^-1 J
+ * (D_P = projection Jacobian of the last sweep), by transposed sweeps that
+ * reuse the forward's SpMV layout.  Errors as vfpi_step, plus VFPI_E_NO_TAPE
+ * for tape == NULL. */
+int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc,
+                       const void* tape, const double* grad_v, const double* grad_lambda,
+                       double* grad_b, double* grad_A_val, double* grad_phi, double* grad_mu,
+                       const vfpi_opts* opts, vfpi_stats* stats, hipStream_t stream);
+
+/* Static description of a return code. */
+const char* vfpi_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VFPI_H */

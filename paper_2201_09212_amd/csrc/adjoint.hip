@@ -1,0 +1,361 @@
+// (compiled as part of vfpi_lib.hip)
+// Adjoint of a converged V-FPI step (FP64).
+//
+// The step's fixed-point map (Sec. IV, Lemma 1 framing) is
+//   f(v) = v* + W J^T P(-Gamma^-1 (J v* + phi e1)),  v* = v - W (A v - b),
+// with P the strict projection (eq. operator).  Holding W constant (the fixed
+// point does not depend on it, consistency remark of Sec. III-B) and writing
+// D_P for P's Jacobian on the branch taken in the last sweep, G = I - W J^T D_P
+// Gamma^-1 J, the adjoint u of a loss with gradients (g_v, g_lam) solves
+//     u = g~ + (I - A W) G^T u,   g~ = g_v - (I - A W) J^T Gamma^-1 D_P^T g_lam.
+// It is iterated in the variables t = G^T u, s = W t:
+//     u^{l+1} = g~ + t^l - A s^l,  t^{l+1} = G^T u^{l+1},  s^{l+1} = W t^{l+1}
+// so every sweep is one product with A plus node-local work, like the forward
+// sweep.  Then, with r = J W u + g_lam and q = u - J^T Gamma^-1 D_P^T r:
+//     dL/db = W q,  dL/dA_ij = -(dL/db)_i v_j,  dL/dphi_m = -(D_P^T r)_n / gamma_m,
+//     dL/dmu_m = (dP/dmu)^T r_m.
+#include <math.h>
+
+#include "gridsync.h"
+#include "internal.h"
+#include "setup.h"
+#include "sweep.h"
+
+namespace vfpi {
+
+struct AdjArgs {
+  int32_t n_nodes, n_contacts, nnzb;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const int32_t* scol;
+  const double* sval;
+  const double* w;
+  const int32_t* cmap;
+  const double* cpack;
+  const double* lamstar;
+  const int32_t* branch;
+  const double* vsol;
+  const double* gv;
+  const double* gl;
+  double* gt;
+  double* U[2];
+  double* T[2];
+  double* S[2];
+  double* E;
+  double* grad_b;
+  double* grad_A;
+  double* grad_phi;
+  double* grad_mu;
+  int32_t max_iters, fixed;
+  double tol;
+  const int32_t* flags;
+  vfpi_stats* stats;
+  double* red;
+  int32_t* ired;
+  uint32_t* sync;
+};
+
+// y = D_P^T x for the contact's branch; *dmu = (dP/dmu)^T x.
+VFPI_DEV void dp_transpose(const double* ls, int br, double mu, const double x[3], double y[3], double* dmu) {
+  if (br == BR_STICK) {
+    y[0] = x[0];
+    y[1] = x[1];
+    y[2] = x[2];
+    *dmu = 0.0;
+    return;
+  }
+  if (br != BR_SLIP) {
+    y[0] = y[1] = y[2] = 0.0;
+    *dmu = 0.0;
+    return;
+  }
+  const double n = ls[0], t1 = ls[1], t2 = ls[2];
+  const double s = sqrt(t1 * t1 + t2 * t2);
+  const double h1 = t1 / s, h2 = t2 / s;
+  const double ht = h1 * x[1] + h2 * x[2];
+  const double k = mu * n / s;
+  y[0] = x[0] + mu * ht;
+  y[1] = k * (x[1] - h1 * ht);
+  y[2] = k * (x[2] - h2 * ht);
+  *dmu = n * ht;
+}
+
+// (G^T u)_i for a node: u - R^T D_P^T R u on a contact node (gamma = w_i), u elsewhere.
+VFPI_DEV void gt_node(const AdjArgs& a, int m, const double u[3], double out[3]) {
+  out[0] = u[0];
+  out[1] = u[1];
+  out[2] = u[2];
+  if (m < 0) return;
+  const double* R = a.cpack + kPack * (int64_t)m;
+  double x[3], y[3], dmu;
+  for (int k = 0; k < 3; ++k) x[k] = R[3 * k] * u[0] + R[3 * k + 1] * u[1] + R[3 * k + 2] * u[2];
+  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+  for (int r = 0; r < 3; ++r) out[r] -= R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
+}
+
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
+  __shared__ double s_red[NW];
+  __shared__ int s_ired[NW];
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = xcd_logical_block(b, G);
+  const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nch = (a.n_nodes + 63) / 64;
+  const int64_t c0 = lb * nch / G, c1 = (lb + 1) * nch / G;
+  const int passes = (int)((c1 - c0 + NW - 1) / NW);
+  const int flags = *a.flags;
+  if (flags != 0) {
+    for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_nodes; k += (int64_t)G * blockDim.x)
+      a.grad_b[k] = 0.0;
+    for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < a.n_contacts; k += (int64_t)G * blockDim.x)
+      a.grad_phi[k] = a.grad_mu[k] = 0.0;
+    if (a.grad_A)
+      for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < 9 * (int64_t)a.nnzb;
+           k += (int64_t)G * blockDim.x)
+        a.grad_A[k] = 0.0;
+    if (b == 0 && threadIdx.x == 0) {
+      a.stats->iters = 0;
+      a.stats->status = flags;
+      a.stats->theta = INFINITY;
+      a.stats->n_open = a.stats->n_stick = a.stats->n_slip = a.stats->reserved = 0;
+    }
+    return;
+  }
+  auto for_my_nodes = [&](auto&& fn) {
+    for (int p = 0; p < passes; ++p) {
+      const int64_t c = c0 + (int64_t)p * NW + slot;
+      const int64_t n0 = c * 64;
+      const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+      fn(n0, cnt);
+    }
+  };
+  // phase A: e = J^T Gamma^-1 D_P^T g_lam (node-local), p = W e into S[1]
+  if (a.gl) {
+    for_my_nodes([&](int64_t n0, int cnt) {
+      if (lane >= cnt) return;
+      const int64_t i = n0 + lane;
+      const int m = a.cmap[i];
+      double e[3] = {0.0, 0.0, 0.0};
+      if (m >= 0) {
+        const double* R = a.cpack + kPack * (int64_t)m;
+        double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
+        dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+        const double gi = 1.0 / R[11];
+        for (int r = 0; r < 3; ++r) e[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
+      }
+      for (int r = 0; r < 3; ++r) {
+        a.E[3 * i + r] = e[r];
+        a.S[1][3 * i + r] = a.w[3 * i + r] * e[r];
+      }
+    });
+    grid_barrier(a.sync, G);
+  }
+  // phase B: g~ = g_v - e + A p; u0 = g~, t0 = G^T u0, s0 = W t0
+  for_my_nodes([&](int64_t n0, int cnt) {
+    const int64_t i = n0 + lane;
+    const bool act = lane < cnt;
+    double Ap[3] = {0.0, 0.0, 0.0};
+    if (a.gl) {
+      const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
+      spmv_rows3<double>(a.scol, a.sval, a.S[1], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, Ap);
+    }
+    if (!act) return;
+    double u[3], t[3];
+    for (int r = 0; r < 3; ++r) u[r] = a.gl ? a.gv[3 * i + r] - a.E[3 * i + r] + Ap[r] : a.gv[3 * i + r];
+    gt_node(a, a.cmap[i], u, t);
+    for (int r = 0; r < 3; ++r) {
+      a.gt[3 * i + r] = u[r];
+      a.U[0][3 * i + r] = u[r];
+      a.T[0][3 * i + r] = t[r];
+      a.S[0][3 * i + r] = a.w[3 * i + r] * t[r];
+    }
+  });
+  grid_barrier(a.sync, G);
+  int cur = 0;
+  if (a.max_iters > 0) {
+    int l = 0;
+    for (;;) {
+      ++l;
+      const int nxt = cur ^ 1;
+      double th2 = 0.0;
+      for_my_nodes([&](int64_t n0, int cnt) {
+        const int64_t i = n0 + lane;
+        const bool act = lane < cnt;
+        const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
+        double As[3];
+        spmv_rows3<double>(a.scol, a.sval, a.S[cur], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, As);
+        if (!act) return;
+        double un[3], tn[3];
+        for (int r = 0; r < 3; ++r) un[r] = a.gt[3 * i + r] + a.T[cur][3 * i + r] - As[r];
+        gt_node(a, a.cmap[i], un, tn);
+        for (int r = 0; r < 3; ++r) {
+          const double d = un[r] - a.U[cur][3 * i + r];
+          th2 += d * d;
+          a.U[nxt][3 * i + r] = un[r];
+          a.T[nxt][3 * i + r] = tn[r];
+          a.S[nxt][3 * i + r] = a.w[3 * i + r] * tn[r];
+        }
+      });
+      th2 = block_sum(th2, s_red);
+      const int zero[3] = {0, 0, 0};
+      const bool stop = grid_residual_step(a.sync, a.red, a.ired, G, lb, th2, zero, l, a.max_iters, a.fixed, a.tol,
+                                           a.stats, s_red, s_ired);
+      cur = nxt;
+      if (stop) break;
+    }
+  } else if (b == 0 && threadIdx.x == 0) {
+    a.stats->iters = 0;
+    a.stats->status = VFPI_S_MAXITER;
+    a.stats->theta = INFINITY;
+    a.stats->n_open = a.stats->n_stick = a.stats->n_slip = a.stats->reserved = 0;
+  }
+  // final gradients (node-local in u; A_bar reads the solution v of neighbours)
+  const double* u_fin = a.U[cur];
+  for_my_nodes([&](int64_t n0, int cnt) {
+    if (lane >= cnt) return;
+    const int64_t i = n0 + lane;
+    const int m = a.cmap[i];
+    double u[3] = {u_fin[3 * i], u_fin[3 * i + 1], u_fin[3 * i + 2]};
+    double q[3] = {u[0], u[1], u[2]};
+    if (m >= 0) {
+      const double* R = a.cpack + kPack * (int64_t)m;
+      const double wb = a.w[3 * i];
+      double rr[3], y[3], dmu;
+      for (int k = 0; k < 3; ++k) {
+        rr[k] = R[3 * k] * (wb * u[0]) + R[3 * k + 1] * (wb * u[1]) + R[3 * k + 2] * (wb * u[2]);
+        if (a.gl) rr[k] += a.gl[3 * (int64_t)m + k];
+      }
+      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], rr, y, &dmu);
+      const double gi = 1.0 / R[11];
+      for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
+      a.grad_phi[m] = -y[0] * gi;
+      a.grad_mu[m] = dmu;
+    }
+    double bb[3];
+    for (int r = 0; r < 3; ++r) {
+      bb[r] = a.w[3 * i + r] * q[r];
+      a.grad_b[3 * i + r] = bb[r];
+    }
+    if (a.grad_A) {
+      const int64_t rp = a.row_ptr[i], re = a.row_ptr[i + 1];
+      for (int64_t k = rp; k < re; ++k) {
+        const int64_t c = a.col_idx[k];
+        const double v0 = a.vsol[3 * c], v1 = a.vsol[3 * c + 1], v2 = a.vsol[3 * c + 2];
+        double* g = a.grad_A + 9 * k;
+        for (int r = 0; r < 3; ++r) {
+          g[3 * r] = -bb[r] * v0;
+          g[3 * r + 1] = -bb[r] * v1;
+          g[3 * r + 2] = -bb[r] * v2;
+        }
+      }
+    }
+  });
+}
+
+}  // namespace vfpi
+
+using namespace vfpi;
+
+extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc, const void* tape,
+                                  const double* grad_v, const double* grad_lambda, double* grad_b, double* grad_A_val,
+                                  double* grad_phi, double* grad_mu, const vfpi_opts* opts, vfpi_stats* stats,
+                                  hipStream_t stream) {
+  if (!ctx || !A || !Jc || !grad_v || !grad_b || !opts || !stats) return VFPI_E_NULL;
+  if (!tape) return VFPI_E_NO_TAPE;
+  const int32_t N = A->n_nodes, nc = Jc->n_contacts;
+  if (N < 0 || nc < 0 || A->nnzb < 0 || Jc->nnzb < 0 || nc > N) return VFPI_E_SHAPE;
+  if (N > 0 && (!A->row_ptr || !A->col_idx || !A->val)) return VFPI_E_NULL;
+  if (nc > 0 && (!Jc->row_ptr || !Jc->col_idx || !Jc->val || !Jc->phi || !Jc->mu || !grad_phi || !grad_mu))
+    return VFPI_E_NULL;
+  if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
+  if (opts->max_iters < 0 || !(opts->tol >= 0.0)) return VFPI_E_OPTS;
+  if (opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
+  if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;
+  if (N == 0) {
+    vfpi_stats h = {0, VFPI_S_MAXITER, 0.0, 0, 0, 0, 0};
+    VFPI_CHECK_HIP(hipMemcpyAsync(stats, &h, sizeof(h), hipMemcpyHostToDevice, stream));
+    return VFPI_OK;
+  }
+  VFPI_CHECK_HIP(hipSetDevice(ctx->device));
+  TapeView tv = tape_view(const_cast<void*>(tape), N, nc);
+  double* cpack = static_cast<double*>(ctx->cpack);
+  double* w = static_cast<double*>(ctx->w);
+
+  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync);
+  if (nc > 0)
+    hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
+                       Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
+                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->flags, 1e-10);
+  // W comes from the forward tape; the row pass rebuilds the interleaved copy of A.
+  RowsArgs ra;
+  ra.nnzb = A->nnzb;
+  ra.w_mode = VFPI_W_USER_DIAG;
+  ra.reuse = false;
+  ra.alpha = 0.0;
+  const int64_t nch = (N + 63) / 64;
+  hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, stream, N, A->row_ptr, A->col_idx,
+                     static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), nullptr, nullptr,
+                     ra, tv.w, ctx->cmap, cpack, w, nullptr, grad_v, tv.v,
+                     ctx->flags);
+  VFPI_CHECK_HIP(hipGetLastError());
+
+  const int64_t n = 3 * (int64_t)N;
+  AdjArgs aa;
+  aa.n_nodes = N;
+  aa.n_contacts = nc;
+  aa.nnzb = A->nnzb;
+  aa.row_ptr = A->row_ptr;
+  aa.col_idx = A->col_idx;
+  aa.scol = ctx->scol;
+  aa.sval = static_cast<const double*>(ctx->sval);
+  aa.w = w;
+  aa.cmap = ctx->cmap;
+  aa.cpack = cpack;
+  aa.lamstar = tv.lamstar;
+  aa.branch = tv.branch;
+  aa.vsol = tv.v;
+  aa.gv = grad_v;
+  aa.gl = grad_lambda;
+  aa.gt = ctx->adj;
+  aa.U[0] = ctx->adj + n;
+  aa.U[1] = ctx->adj + 2 * n;
+  aa.T[0] = ctx->adj + 3 * n;
+  aa.T[1] = ctx->adj + 4 * n;
+  aa.S[0] = ctx->adj + 5 * n;
+  aa.S[1] = ctx->adj + 6 * n;
+  aa.E = ctx->adj + 7 * n;
+  aa.grad_b = grad_b;
+  aa.grad_A = grad_A_val;
+  aa.grad_phi = grad_phi;
+  aa.grad_mu = grad_mu;
+  aa.max_iters = opts->max_iters;
+  aa.fixed = opts->fixed_iters;
+  aa.tol = opts->tol;
+  aa.flags = ctx->flags;
+  aa.stats = stats;
+  aa.red = ctx->red;
+  aa.ired = ctx->ired;
+  aa.sync = ctx->sync;
+
+  const int kind = opts->variant & 0xff;
+  const int grid_req = (opts->variant >> 16) & 0xffff;
+  constexpr int NW = 4;
+  auto kern = k_adjoint<NW>;
+  const int threads = 64 * NW;
+  const int64_t want = (nch + NW - 1) / NW;
+  int64_t g = 1;
+  if (kind != 3) {
+    int per_cu = 0;
+    VFPI_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0));
+    int64_t cap = (int64_t)per_cu * ctx->num_cu;
+    if (cap > kMaxGrid - 1) cap = kMaxGrid - 1;
+    g = want < cap ? want : cap;
+    if (grid_req > 0 && grid_req < g) g = grid_req;
+    if (g < 1) g = 1;
+    if (g > 8) g -= g % 8;
+  }
+  void* params[] = {&aa};
+  VFPI_CHECK_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, stream));
+  return VFPI_OK;
+}

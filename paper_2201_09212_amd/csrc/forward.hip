@@ -1,0 +1,285 @@
+// (compiled as part of vfpi_lib.hip)
+// Plain FP64 V-FPI step: setup kernels + one persistent kernel that runs the
+// whole iteration (Alg. 1 inner loop) on the device, with a deterministic
+// grid-wide residual reduction and early exit.
+#include <math.h>
+
+#include "internal.h"
+#include "setup.h"
+#include "sweep.h"
+#include "gridsync.h"
+
+namespace vfpi {
+
+__global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t* sync) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n_nodes) cmap[i] = -1;
+  if (i == 0) {
+    flags[0] = 0;
+    for (int k = 0; k < kSyncWords; ++k) sync[k] = 0u;
+  }
+}
+
+template <class T>
+__global__ void k_contacts(int32_t nc, int32_t nnzb_c, const int32_t* crp, const int32_t* ccol, const T* cval,
+                           const T* phi, const T* mu, int32_t n_nodes, int32_t* cmap, T* cpack, int32_t* flags,
+                           double orth_tol) {
+  int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (m < nc) contact_setup<T>(m, nnzb_c, crp, ccol, cval, phi, mu, 0, n_nodes, cmap, cpack, flags, orth_tol);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_rows(int32_t n_nodes, const int32_t* row_ptr, const int32_t* col_idx,
+                                              const T* val, int32_t* scol, T* sval, double* diag, double* rn2,
+                                              RowsArgs ra, const T* w_user, const int32_t* cmap, T* cpack, T* w,
+                                              double* tape_w, const T* bvec, const T* vvec, int32_t* flags) {
+  const int64_t chunk = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t n0 = chunk * 64;
+  if (n0 >= n_nodes) return;  // whole wave leaves together
+  const int cnt = (int)min<int64_t>(64, n_nodes - n0);
+  rows_chunk<T>(n0, cnt, threadIdx.x & 63, row_ptr, col_idx, val, scol, sval, 0, n_nodes, diag, rn2, ra, w_user,
+                cmap, cpack, w, tape_w, bvec, vvec, flags);
+}
+
+struct GridArgs {
+  SweepData<double> d;
+  int32_t n_nodes, n_contacts;
+  double* v_user;
+  double* v_alt;
+  double* tape_v;
+  int32_t max_iters, fixed;
+  double tol;
+  const int32_t* flags;
+  vfpi_stats* stats;
+  double* red;
+  int32_t* ired;
+  uint32_t* sync;
+};
+
+VFPI_DEV void write_stats(vfpi_stats* st, int iters, int status, double theta, int o, int s, int l) {
+  st->iters = iters;
+  st->status = status;
+  st->theta = theta;
+  st->n_open = o;
+  st->n_stick = s;
+  st->n_slip = l;
+  st->reserved = 0;
+}
+
+// Persistent V-FPI kernel.  TPN = threads per node (1: a lane owns a node's
+// three rows; 3: three waves own rows 0/1/2 of the same 64 nodes), NW = chunk
+// slots per workgroup.  Needs a cooperative launch when gridDim.x > 1 (all
+// workgroups resident: they meet once per sweep at the residual barrier).
+template <int TPN, int NW>
+__global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
+  __shared__ double s_vs[2][TPN == 3 ? NW : 1][3][64];
+  __shared__ double s_red[TPN * NW];
+  __shared__ int s_ired[TPN * NW];
+
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = xcd_logical_block(b, G);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = wave / TPN, r = (TPN == 3) ? wave % 3 : 0;
+  const int64_t nch = (a.n_nodes + 63) / 64;
+  const int64_t c0 = lb * nch / G, c1 = (lb + 1) * nch / G;
+  const int passes = (int)((c1 - c0 + NW - 1) / NW);
+
+  const int flags = *a.flags;
+  if (flags != 0 || a.max_iters <= 0) {
+    for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_contacts;
+         k += (int64_t)G * blockDim.x)
+      a.d.lambda[k] = 0.0;
+    if (b == 0 && threadIdx.x == 0)
+      write_stats(a.stats, 0, flags ? flags : VFPI_S_MAXITER, INFINITY, 0, 0, 0);
+    return;
+  }
+
+  double* vcur = a.v_user;
+  double* vnext = a.v_alt;
+  int l = 0;
+  for (;;) {
+    ++l;
+    double th2 = 0.0;
+    int cb[3] = {0, 0, 0};
+    for (int p = 0; p < passes; ++p) {
+      const int64_t c = c0 + (int64_t)p * NW + slot;
+      const int64_t n0 = c * 64;
+      const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+      if (TPN == 3)
+        sweep_chunk_row<double>(a.d, vcur, vnext, n0, cnt, lane, r, s_vs[p & 1][TPN == 3 ? slot : 0], th2, cb);
+      else
+        sweep_chunk_node<double>(a.d, vcur, vnext, n0, cnt, lane, th2, cb);
+    }
+    th2 = block_sum(th2, s_red);
+    int cnt3[3];
+    cnt3[0] = block_sum_int(cb[0], s_ired);
+    cnt3[1] = block_sum_int(cb[1], s_ired);
+    cnt3[2] = block_sum_int(cb[2], s_ired);
+    const bool stop = grid_residual_step(a.sync, a.red, a.ired, G, lb, th2, cnt3, l, a.max_iters, a.fixed, a.tol,
+                                         a.stats, s_red, s_ired);
+    double* t = vcur;
+    vcur = vnext;
+    vnext = t;
+    if (stop) break;
+  }
+  // The final iterate is in vcur.  Each thread copies only entries it wrote
+  // itself in the last sweep, so no further barrier is needed.
+  if (vcur != a.v_user || a.tape_v) {
+    for (int p = 0; p < passes; ++p) {
+      const int64_t c = c0 + (int64_t)p * NW + slot;
+      const int64_t n0 = c * 64;
+      const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+      if (lane < cnt) {
+        const int64_t i = n0 + lane;
+        for (int rr = (TPN == 3 ? r : 0); rr < (TPN == 3 ? r + 1 : 3); ++rr) {
+          const double x = vcur[3 * i + rr];
+          if (vcur != a.v_user) a.v_user[3 * i + rr] = x;
+          if (a.tape_v) a.tape_v[3 * i + rr] = x;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace vfpi
+
+using namespace vfpi;
+
+namespace {
+
+struct Variant {
+  int kind;   // 1: grid TPN=1, 2: grid TPN=3, 3: single workgroup TPN=1, 4: single workgroup TPN=3
+  int nw;     // chunk slots per workgroup
+  int grid;   // workgroups (0 = auto)
+};
+
+Variant decode_variant(int32_t v, int32_t n_nodes) {
+  Variant x;
+  x.kind = v & 0xff;
+  x.nw = (v >> 8) & 0xff;
+  x.grid = (v >> 16) & 0xffff;
+  if (x.kind == 0) x.kind = (n_nodes <= 1024) ? 3 : 2;
+  if (x.nw == 0) x.nw = (x.kind == 3) ? 16 : (x.kind == 4 ? 5 : (x.kind == 1 ? 4 : 1));
+  return x;
+}
+
+template <int TPN, int NW>
+hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool single, hipStream_t st) {
+  auto kern = k_vfpi_grid<TPN, NW>;
+  const int threads = 64 * TPN * NW;
+  const int64_t nch = (n_nodes + 63) / 64;
+  const int64_t want = (nch + NW - 1) / NW;
+  if (single) {
+    hipLaunchKernelGGL(kern, dim3(1), dim3(threads), 0, st, ga);
+    return hipGetLastError();
+  }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
+  if (e != hipSuccess) return e;
+  int64_t cap = (int64_t)per_cu * num_cu;
+  if (cap > kMaxGrid - 1) cap = kMaxGrid - 1;
+  int64_t g = want < cap ? want : cap;
+  if (grid_req > 0 && grid_req < g) g = grid_req;
+  if (g < 1) g = 1;
+  if (g > 8) g -= g % 8;  // keep the XCD-aware numbering exact
+  GridArgs arg = ga;
+  void* params[] = {&arg};
+  return hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, st);
+}
+
+}  // namespace
+
+extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc, double* v,
+                         double* lambda, const vfpi_opts* opts, vfpi_stats* stats, void* tape, hipStream_t stream) {
+  if (!ctx || !A || !b || !Jc || !v || !opts || !stats) return VFPI_E_NULL;
+  const int32_t N = A->n_nodes, nc = Jc->n_contacts;
+  if (N < 0 || nc < 0 || A->nnzb < 0 || Jc->nnzb < 0 || nc > N) return VFPI_E_SHAPE;
+  if (N > 0 && (!A->row_ptr || !A->col_idx || !A->val)) return VFPI_E_NULL;
+  if (nc > 0 && (!Jc->row_ptr || !Jc->col_idx || !Jc->val || !Jc->phi || !Jc->mu || !lambda)) return VFPI_E_NULL;
+  if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
+  int rc = vfpi_check_opts(opts, false);
+  if (rc) return rc;
+  if (opts->w_mode == VFPI_W_BB1 || opts->w_mode == VFPI_W_BB2) return VFPI_E_UNSUPPORTED;
+  if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;  // a row with two blocks: D-contacts
+  if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
+  if (N == 0) {
+    vfpi_stats h = {0, VFPI_S_MAXITER, 0.0, 0, 0, 0, 0};
+    VFPI_CHECK_HIP(hipMemcpyAsync(stats, &h, sizeof(h), hipMemcpyHostToDevice, stream));
+    return VFPI_OK;
+  }
+  VFPI_CHECK_HIP(hipSetDevice(ctx->device));
+
+  TapeView tv = {nullptr, nullptr, nullptr, nullptr};
+  if (tape) tv = tape_view(tape, N, nc);
+  double* cpack = static_cast<double*>(ctx->cpack);
+  double* w = static_cast<double*>(ctx->w);
+
+  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync);
+  if (nc > 0)
+    hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
+                       Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
+                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->flags, 1e-10);
+  RowsArgs ra;
+  ra.nnzb = A->nnzb;
+  ra.w_mode = opts->w_mode;
+  ra.reuse = opts->reuse_w != 0;
+  ra.alpha = opts->alpha_user;
+  const int64_t nch = (N + 63) / 64;
+  hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, stream, N, A->row_ptr, A->col_idx,
+                     static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), ctx->diag,
+                     ctx->rn2, ra, static_cast<const double*>(opts->w_user), ctx->cmap, cpack, w, tv.w, b, v,
+                     ctx->flags);
+  VFPI_CHECK_HIP(hipGetLastError());
+  ctx->stats_nodes = N;
+
+  GridArgs ga;
+  ga.d.row_ptr = A->row_ptr;
+  ga.d.scol = ctx->scol;
+  ga.d.sval = static_cast<const double*>(ctx->sval);
+  ga.d.b = b;
+  ga.d.w = w;
+  ga.d.cmap = ctx->cmap;
+  ga.d.cpack = cpack;
+  ga.d.lambda = lambda;
+  ga.d.tape_lamstar = tv.lamstar;
+  ga.d.tape_branch = tv.branch;
+  ga.d.proj = opts->projection;
+  ga.n_nodes = N;
+  ga.n_contacts = nc;
+  ga.v_user = v;
+  ga.v_alt = static_cast<double*>(ctx->vbuf);
+  ga.tape_v = tv.v;
+  ga.max_iters = opts->max_iters;
+  ga.fixed = opts->fixed_iters;
+  ga.tol = opts->tol;
+  ga.flags = ctx->flags;
+  ga.stats = stats;
+  ga.red = ctx->red;
+  ga.ired = ctx->ired;
+  ga.sync = ctx->sync;
+
+  Variant vr = decode_variant(opts->variant, N);
+  hipError_t e;
+  switch (vr.kind) {
+    case 1:
+      e = (vr.nw <= 1) ? launch_grid<1, 1>(ga, vr.grid, ctx->num_cu, N, false, stream)
+        : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, ctx->num_cu, N, false, stream)
+                       : launch_grid<1, 4>(ga, vr.grid, ctx->num_cu, N, false, stream);
+      break;
+    case 2:
+      e = (vr.nw <= 1) ? launch_grid<3, 1>(ga, vr.grid, ctx->num_cu, N, false, stream)
+                       : launch_grid<3, 2>(ga, vr.grid, ctx->num_cu, N, false, stream);
+      break;
+    case 3:
+      e = (vr.nw <= 4) ? launch_grid<1, 4>(ga, 1, ctx->num_cu, N, true, stream)
+                       : launch_grid<1, 16>(ga, 1, ctx->num_cu, N, true, stream);
+      break;
+    case 4:
+      e = launch_grid<3, 5>(ga, 1, ctx->num_cu, N, true, stream);
+      break;
+    default:
+      return VFPI_E_OPTS;
+  }
+  return e == hipSuccess ? VFPI_OK : VFPI_E_HIP;
+}

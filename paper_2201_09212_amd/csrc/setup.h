@@ -1,0 +1,176 @@
+// Per-step setup shared by the plain, batched and adjoint kernels:
+//  * contact records: validate each J_c block row (one SO(3) block at a
+//    node, eq. jcnode), build the node -> contact map, pack R, phi, mu;
+//  * block rows of A: copy into the chunk-interleaved layout (see common.h),
+//    accumulate a_dd and ||A_d*||^2, and form the step sizes W (Sec. IV-C.1)
+//    and gamma_m = w_i of Prop. 3.
+#pragma once
+
+#include "common.h"
+
+namespace vfpi {
+
+template <class T>
+VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict__ crp,
+                            const int32_t* __restrict__ ccol, const T* __restrict__ cval,
+                            const T* __restrict__ phi, const T* __restrict__ mu, int64_t node_lo,
+                            int64_t node_hi, int32_t* cmap, T* cpack, int32_t* flag, double orth_tol) {
+  int64_t r0 = crp[m], r1 = crp[m + 1];
+  if (r1 - r0 != 1 || r0 < 0 || r1 > nnzb_c) {
+    set_flag(flag, VFPI_S_NOT_NODAL);
+    return;
+  }
+  int64_t i = ccol[r0];
+  if (i < node_lo || i >= node_hi) {
+    set_flag(flag, VFPI_S_BAD_PATTERN);
+    return;
+  }
+  T R[9];
+  bool fin = true;
+  for (int e = 0; e < 9; ++e) {
+    R[e] = cval[9 * r0 + e];
+    fin &= finite(R[e]);
+  }
+  T ph = phi[m], mm = mu[m];
+  fin &= finite(ph) && finite(mm);
+  if (!fin) {
+    set_flag(flag, VFPI_S_NONFINITE);
+    return;
+  }
+  if (!(mm >= T(0))) set_flag(flag, VFPI_S_BAD_MU);
+  double err = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double d = (double)R[3 * a] * R[3 * b] + (double)R[3 * a + 1] * R[3 * b + 1] +
+                 (double)R[3 * a + 2] * R[3 * b + 2] - (a == b ? 1.0 : 0.0);
+      err = fmax(err, fabs(d));
+    }
+  if (!(err <= orth_tol)) set_flag(flag, VFPI_S_NOT_ORTHONORMAL);
+  int old = atomicCAS(cmap + i, -1, (int)m);
+  if (old != -1) set_flag(flag, VFPI_S_SHARED_NODE);
+  T* pk = cpack + kPack * m;
+  for (int e = 0; e < 9; ++e) pk[e] = R[e];
+  pk[9] = ph;
+  pk[10] = mm;
+}
+
+struct RowsArgs {
+  int32_t nnzb;
+  int w_mode;
+  bool reuse;
+  double alpha;
+};
+
+// One wave converts one chunk of <= 64 consecutive nodes [n0, n0 + cnt).
+// Every lane of the wave must call.  Nodes of the chunk must lie in
+// [node_lo, node_hi), and so must every column index (else BAD_PATTERN).
+// bvec / vvec (nullable) are checked for NaN/Inf along with the row.
+template <class T>
+VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restrict__ row_ptr,
+                         const int32_t* __restrict__ col_idx, const T* __restrict__ val,
+                         int32_t* __restrict__ scol, T* __restrict__ sval, int64_t node_lo,
+                         int64_t node_hi, double* __restrict__ diag, double* __restrict__ rn2,
+                         const RowsArgs ra, const T* __restrict__ w_user, const int32_t* __restrict__ cmap,
+                         T* __restrict__ cpack, T* __restrict__ w, double* __restrict__ tape_w,
+                         const T* __restrict__ bvec, const T* __restrict__ vvec, int32_t* flag) {
+  const int64_t i = n0 + lane;
+  const bool act = lane < cnt;
+  int64_t rp = 0;
+  int nk = 0;
+  bool bad = false;
+  if (act) {
+    int64_t r1;
+    rp = row_ptr[i];
+    r1 = row_ptr[i + 1];
+    nk = (int)(r1 - rp);
+    bad = rp < 0 || r1 < rp || r1 > ra.nnzb || (i == 0 && rp != 0);
+  }
+  if (ballot(bad) != 0) {  // row offsets unusable: skip the whole chunk
+    if (lane == 0) set_flag(flag, VFPI_S_BAD_PATTERN);
+    return;
+  }
+  const int64_t base = row_ptr[n0];
+  double d[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+  bool has_diag = false, fin = true, badcol = false;
+  int64_t off = 0;
+  for (int k = 0;; ++k) {
+    uint64_t mask = ballot(k < nk);
+    if (mask == 0) break;
+    int c_ = __popcll(mask);
+    if (k < nk) {
+      int pos = lanes_below(mask, lane);
+      int64_t q = base + off;
+      int64_t c = col_idx[rp + k];
+      if (c < node_lo || c >= node_hi) {
+        badcol = true;
+        c = i;
+      }
+      scol[q + pos] = (int32_t)c;
+      const T* src = val + 9 * (rp + k);
+      T x[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        x[e] = src[e];
+        sval[9 * q + (int64_t)e * c_ + pos] = x[e];
+        fin &= finite(x[e]);
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) s[r] += (double)x[3 * r + cc] * (double)x[3 * r + cc];
+      if (c == i) {
+        has_diag = true;
+        d[0] = x[0];
+        d[1] = x[4];
+        d[2] = x[8];
+      }
+    }
+    off += c_;
+  }
+  if (!act) return;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    if (bvec) fin &= finite(bvec[3 * i + r]);
+    if (vvec) fin &= finite(vvec[3 * i + r]);
+  }
+  if (badcol) set_flag(flag, VFPI_S_BAD_PATTERN);
+  if (!fin) set_flag(flag, VFPI_S_NONFINITE);
+  if (ra.reuse) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      d[r] = diag[3 * i + r];
+      s[r] = rn2[3 * i + r];
+    }
+  } else if (diag) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      diag[3 * i + r] = d[r];
+      rn2[3 * i + r] = s[r];
+    }
+  }
+  if (!has_diag || !(d[0] > 0.0) || !(d[1] > 0.0) || !(d[2] > 0.0)) set_flag(flag, VFPI_S_NONPOS_DIAG);
+  const int m = cmap[i];
+  double wr[3];
+  if (ra.w_mode == VFPI_W_FROBENIUS) {
+    if (m >= 0) {
+      double wb = (d[0] + d[1] + d[2]) / (s[0] + s[1] + s[2]);
+      wr[0] = wr[1] = wr[2] = wb;
+    } else {
+      for (int r = 0; r < 3; ++r) wr[r] = d[r] / s[r];
+    }
+  } else if (ra.w_mode == VFPI_W_USER_DIAG) {
+    for (int r = 0; r < 3; ++r) wr[r] = (double)w_user[3 * i + r];
+    if (!(wr[0] > 0.0 && wr[1] > 0.0 && wr[2] > 0.0) || !finite(wr[0] + wr[1] + wr[2]) ||
+        (m >= 0 && (wr[0] != wr[1] || wr[1] != wr[2])))
+      set_flag(flag, VFPI_S_BAD_W);
+  } else {
+    wr[0] = wr[1] = wr[2] = ra.alpha;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    w[3 * i + r] = (T)wr[r];
+    if (tape_w) tape_w[3 * i + r] = wr[r];
+  }
+  if (m >= 0) cpack[kPack * (int64_t)m + 11] = (T)wr[0];
+}
+
+}  // namespace vfpi

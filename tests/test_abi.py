@@ -1,0 +1,71 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/vfpi.h declares, and rejects bad arguments synchronously before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2201_09212_amd as vf
+from paper_2201_09212_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vfpi.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(vfpi_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    assert _declared() == sorted(_abi.ENTRY_POINTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = vf.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_error_strings():
+    for code in range(-7, 1):
+        assert vf.vfpi_error_string(code) != "unknown error code"
+    assert vf.vfpi_error_string(-99) == "unknown error code"
+
+
+def test_tape_bytes():
+    assert vf.vfpi_tape_bytes(0, 0) == 0
+    assert vf.vfpi_tape_bytes(100, 100) == 7680  # 48*100 + 28*100 = 7600 -> 256-aligned
+    assert vf.vfpi_tape_bytes(1, 0) == 256
+    assert vf.vfpi_tape_bytes(-1, 0) == _abi.VFPI_E_SHAPE
+
+
+def test_null_and_shape_errors_before_device_work():
+    lib = vf.load()
+    A = _abi.vfpi_bsr(4, 4, None, None, None)
+    Jc = _abi.vfpi_contacts(0, 0, None, None, None, None, None)
+    o = vf.make_opts()
+    assert lib.vfpi_step(None, ctypes.byref(A), None, ctypes.byref(Jc), None, None, ctypes.byref(o), None, None,
+                         None) == _abi.VFPI_E_NULL
+    assert lib.vfpi_step_batched(None, 1, None, None, None, ctypes.byref(A), None, ctypes.byref(Jc), None, None,
+                                 ctypes.byref(o), None, None) == _abi.VFPI_E_NULL
+    assert lib.vfpi_step_backward(None, ctypes.byref(A), ctypes.byref(Jc), None, None, None, None, None, None,
+                                  None, ctypes.byref(o), None, None) == _abi.VFPI_E_NULL
+    assert lib.vfpi_create(None, 1, 1, 1, 0) == _abi.VFPI_E_NULL
+    h = ctypes.c_void_p()
+    assert lib.vfpi_create(ctypes.byref(h), -1, 1, 1, 0) == _abi.VFPI_E_SHAPE
+    assert h.value is None
+    assert lib.vfpi_destroy(None) == _abi.VFPI_OK
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        _abi._lib_saved = _abi._lib
+        try:
+            _abi._lib = None
+            _abi.load(str(tmp_path / "nope.so"))
+        finally:
+            _abi._lib = _abi._lib_saved

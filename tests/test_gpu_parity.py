@@ -1,0 +1,193 @@
+"""FP64 HIP path vs the FP64 oracle, element by element, at a fixed sweep
+count (bar: 1e-9 relative on v and lambda), across every kernel variant,
+ragged sizes, the full-size cloth and FEM workloads, and the edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_09212_amd as vf
+import scenes
+from paper_2201_09212_amd import _abi
+from tests.gpu_util import gpu_step, rel, say, solver_for, upload
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+# kind | chunk slots << 8 | workgroup cap << 16
+VARIANTS = {
+    "wg1_node16": 3,
+    "wg1_node4": 3 | (4 << 8),
+    "wg1_row5": 4,
+    "grid_node1": 1 | (1 << 8),
+    "grid_node4": 1 | (4 << 8),
+    "grid_row1": 2,
+    "grid_row2": 2 | (2 << 8),
+    "grid_node4_cap8": 1 | (4 << 8) | (8 << 16),
+    "grid_row1_cap16": 2 | (16 << 16),
+}
+
+CASES = [(1, 1), (5, 0), (5, 5), (63, 20), (64, 64), (65, 30), (130, 77), (700, 300)]
+
+
+def _compare(p, L, variant, **kw):
+    ref = oracle.vfpi(p, max_iters=L, fixed_iters=True, **{k: v for k, v in kw.items() if k in ("w_mode", "w_user", "alpha_user", "projection")})
+    gkw = {k: v for k, v in kw.items() if k in ("w_mode", "projection")}
+    if "w_user" in kw:
+        gkw["w_user"] = torch.as_tensor(kw["w_user"], device="cuda")
+    if "alpha_user" in kw:
+        gkw["alpha"] = kw["alpha_user"]
+    v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, variant=variant, **gkw)
+    ev, el = rel(v, ref["v"]), rel(lam, ref["lam"])
+    say(f"  N={p.n_nodes} nc={p.n_contacts} L={L} variant={variant:#x} rel_v={ev:.2e} rel_lam={el:.2e}")
+    assert st["status"] == _abi.VFPI_S_MAXITER and st["iters"] == L
+    assert ev <= TOL and el <= TOL
+    counts = np.bincount(ref["branch"], minlength=3) if p.n_contacts else np.zeros(3, int)
+    assert [st["n_open"], st["n_stick"], st["n_slip"]] == counts.tolist()
+    return st
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("n,nc", CASES)
+def test_random_parity_all_variants(n, nc, variant):
+    p = scenes.random_problem(n, nc, 11 * n + nc, degree=5.0, phi_scale=0.5)
+    for L in (1, 7, 40):
+        _compare(p, L, VARIANTS[variant])
+
+
+@pytest.mark.parametrize("mode", ["diag", "scalar", "proximal"])
+def test_user_w_and_proximal_parity(mode):
+    p = scenes.random_problem(300, 120, 5, degree=5.0, phi_scale=0.5)
+    kw = {}
+    if mode == "diag":
+        w = oracle.frobenius_w(p, *oracle.row_stats(oracle.system_matrix(p))) * 0.8
+        kw = {"w_mode": "diag", "w_user": w}
+    elif mode == "scalar":
+        kw = {"w_mode": "scalar", "alpha_user": 0.9 * oracle.core.gershgorin_alpha(oracle.system_matrix(p))}
+    else:
+        kw = {"projection": "proximal"}
+    for variant in (3, 2, 1 | (4 << 8)):
+        _compare(p, 25, variant, **kw)
+
+
+def test_cloth10_fixed_and_converged():
+    sc, x, v = scenes.cloth_cfg1(0)
+    p = sc.assemble(x, v)
+    for variant in (0, 3, 4, 2):
+        _compare(p, 50, variant)
+    ref = oracle.vfpi(p, max_iters=1000, tol=1e-10)
+    v_, lam, st, _ = gpu_step(p, max_iters=1000, tol=1e-10)
+    say(f"  cloth10 converged: oracle {ref['iters']} sweeps, gpu {st['iters']}, theta {st['theta']:.2e}")
+    assert st["status"] == _abi.VFPI_S_CONVERGED
+    assert abs(st["iters"] - ref["iters"]) <= 1
+    assert rel(v_, ref["v"]) <= 1e-9
+
+
+def test_cloth128_full_size():
+    sc, x, v = scenes.cloth_cfg2(0)
+    p = sc.assemble(x, v)
+    for variant in (0, 1 | (4 << 8), 2 | (2 << 8)):
+        _compare(p, 50, variant)
+
+
+def test_fem_full_size():
+    sc, x, v = scenes.fem_cfg3(0)
+    p = sc.assemble(x, v)
+    for variant in (0, 1 | (4 << 8)):
+        _compare(p, 20, variant)
+
+
+def test_inclined_plane_analytic_on_gpu():
+    alpha = np.array([0.2, 0.2, 0.6, 0.6])
+    mu = np.tan(alpha) + np.array([-1e-6, 1e-6, -1e-6, 1e-6])
+    p = scenes.inclined_plane_particles(alpha, mu, mass=2.0, h=0.01, g=9.81)
+    v, lam, st, _ = gpu_step(p, max_iters=3, fixed_iters=True)
+    for k in range(4):
+        slide = mu[k] < np.tan(alpha[k])
+        sp = 0.01 * 9.81 * (np.sin(alpha[k]) - mu[k] * np.cos(alpha[k])) if slide else 0.0
+        exp = sp * np.array([np.cos(alpha[k]), 0.0, -np.sin(alpha[k])])
+        np.testing.assert_allclose(v[3 * k:3 * k + 3], exp, atol=1e-15)
+    assert [st["n_open"], st["n_stick"], st["n_slip"]] == [0, 2, 2]
+
+
+def test_deterministic_bitwise():
+    sc, x, v = scenes.cloth_cfg2(1)
+    p = sc.assemble(x, v)
+    s = solver_for(p)
+    a = gpu_step(p, solver=s, max_iters=30, fixed_iters=True)
+    b = gpu_step(p, solver=s, max_iters=30, fixed_iters=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["theta"] == b[2]["theta"]
+
+
+def test_zero_iterations_and_no_contacts():
+    p = scenes.random_problem(100, 40, 3)
+    v, lam, st, _ = gpu_step(p, max_iters=0)
+    assert np.array_equal(v, p.v0) and np.all(lam == 0) and st["iters"] == 0
+    p0 = scenes.random_problem(100, 0, 3)
+    _compare(p0, 10, 0)
+    ref = oracle.vfpi(p0, max_iters=5000, tol=1e-13)
+    v, lam, st, _ = gpu_step(p0, max_iters=5000, tol=1e-13)
+    assert rel(v, ref["v"]) <= 1e-9
+
+
+def _status_of(p, **kw):
+    v, lam, st, _ = gpu_step(p, max_iters=10, **kw)
+    assert st["iters"] == 0 and np.array_equal(v, p.v0) and np.all(lam == 0)
+    return st["status"]
+
+
+def test_device_detected_data_errors():
+    p = scenes.random_problem(80, 10, 2)
+    bad = scenes.Problem(**{**p.__dict__, "c_node": np.array([1, 1] + list(p.c_node[2:]))})
+    assert _status_of(bad) & _abi.VFPI_S_SHARED_NODE
+    R = p.R.copy()
+    R[3, 0, 0] += 1e-6
+    assert _status_of(scenes.Problem(**{**p.__dict__, "R": R})) & _abi.VFPI_S_NOT_ORTHONORMAL
+    b = p.b.copy()
+    b[7] = np.inf
+    assert _status_of(scenes.Problem(**{**p.__dict__, "b": b})) & _abi.VFPI_S_NONFINITE
+    val = p.val.copy()
+    d = p.row_ptr[4] + int(np.nonzero(p.col_idx[p.row_ptr[4]:p.row_ptr[5]] == 4)[0][0])
+    val[d, 1, 1] = -1.0
+    assert _status_of(scenes.Problem(**{**p.__dict__, "val": val})) & _abi.VFPI_S_NONPOS_DIAG
+    col = p.col_idx.copy()
+    col[5] = 80
+    assert _status_of(scenes.Problem(**{**p.__dict__, "col_idx": col})) & _abi.VFPI_S_BAD_PATTERN
+    mu = p.mu.copy()
+    mu[0] = -0.1
+    assert _status_of(scenes.Problem(**{**p.__dict__, "mu": mu})) & _abi.VFPI_S_BAD_MU
+    w = np.full(p.n, 0.1)
+    w[3 * p.c_node[0]] = 0.2
+    assert _status_of(p, w_mode="diag", w_user=torch.as_tensor(w, device="cuda")) & _abi.VFPI_S_BAD_W
+
+
+def test_synchronous_argument_errors():
+    p = scenes.random_problem(50, 10, 4, n_d_contacts=3)
+    s = vf.Solver(50, p.nnzb, 10)
+    A, Jc, b, v = upload(p)
+    with pytest.raises(vf.VfpiError, match="not supported"):
+        s.step(A, b, Jc, v)
+    small = vf.Solver(10, 10, 1)
+    p2 = scenes.random_problem(50, 5, 4)
+    A, Jc, b, v = upload(p2)
+    with pytest.raises(vf.VfpiError, match="capacity"):
+        small.step(A, b, Jc, v)
+    s2 = solver_for(p2)
+    with pytest.raises(vf.VfpiError, match="invalid option"):
+        s2.step(A, b, Jc, v, max_iters=-1)
+    with pytest.raises(vf.VfpiError, match="invalid option"):
+        s2.step(A, b, Jc, v, w_mode="scalar", alpha=0.0)
+
+
+def test_reuse_w_matches_oracle_with_previous_row_sums():
+    sc, x, v = scenes.cloth_cfg1(0)
+    p1 = sc.assemble(x, v)
+    x2 = x + 0.001 * np.random.default_rng(0).normal(size=x.shape)
+    p2 = sc.assemble(x2, v)
+    s = vf.Solver(p2.n_nodes, p2.nnzb, p2.n_nodes)
+    gpu_step(p1, solver=s, max_iters=5)
+    v2, lam2, st, _ = gpu_step(p2, solver=s, max_iters=40, fixed_iters=True, reuse_w=True)
+    stats1 = oracle.row_stats(oracle.system_matrix(p1))
+    ref = oracle.vfpi(p2, max_iters=40, fixed_iters=True, stats=stats1)
+    assert rel(v2, ref["v"]) <= TOL and rel(lam2, ref["lam"]) <= TOL
