@@ -192,6 +192,16 @@ int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc
                        double* grad_b, double* grad_A_val, double* grad_phi, double* grad_mu,
                        const vfpi_opts* opts, vfpi_stats* stats, hipStream_t stream);
 
+/* Profiling aid.  While enabled on a context, vfpi_step, vfpi_step_batched
+ * and vfpi_step_backward record HIP events on their stream before the setup
+ * kernels, between setup and the solve kernel, and after the solve kernel
+ * (do not enable it for calls captured into a graph).  vfpi_timing_read
+ * waits for the last call's events and returns the two durations in
+ * milliseconds.  Errors: VFPI_E_NULL, VFPI_E_OPTS (read without an enabled,
+ * recorded call), VFPI_E_HIP. */
+int vfpi_timing_enable(vfpi_ctx* ctx, int32_t on);
+int vfpi_timing_read(vfpi_ctx* ctx, float* setup_ms, float* solve_ms);
+
 /* Static description of a return code. */
 const char* vfpi_error_string(int code);
 

@@ -8,6 +8,7 @@ picks launch variants.  Importing the package does not load the library; the
 first call does, and raises if it has not been built.
 """
 from ._abi import (VfpiError, load, vfpi_create, vfpi_destroy, vfpi_error_string, vfpi_step, vfpi_step_backward,
+                   vfpi_timing_enable, vfpi_timing_read,
                    vfpi_step_batched, vfpi_tape_bytes)
 from .solver import Bsr, Contacts, Solver, bsr_from_arrays, contacts_from_arrays, make_opts, new_stats, read_stats
 

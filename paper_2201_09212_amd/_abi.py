@@ -39,7 +39,7 @@ VFPI_PROJ_STRICT = 0
 VFPI_PROJ_PROXIMAL = 1
 
 ENTRY_POINTS = ("vfpi_create", "vfpi_destroy", "vfpi_tape_bytes", "vfpi_step", "vfpi_step_batched",
-                "vfpi_step_backward", "vfpi_error_string")
+                "vfpi_step_backward", "vfpi_timing_enable", "vfpi_timing_read", "vfpi_error_string")
 
 
 class vfpi_bsr(ctypes.Structure):
@@ -97,6 +97,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vfpi_step_backward.argtypes = [P, ctypes.POINTER(vfpi_bsr), ctypes.POINTER(vfpi_contacts), P, P, P, P, P,
                                        P, P, ctypes.POINTER(vfpi_opts), P, P]
     lib.vfpi_step_backward.restype = ctypes.c_int
+    lib.vfpi_timing_enable.argtypes = [P, I32]
+    lib.vfpi_timing_enable.restype = ctypes.c_int
+    lib.vfpi_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    lib.vfpi_timing_read.restype = ctypes.c_int
     lib.vfpi_error_string.argtypes = [ctypes.c_int]
     lib.vfpi_error_string.restype = ctypes.c_char_p
     _lib = lib
@@ -150,3 +154,14 @@ def vfpi_step_backward(ctx, A: vfpi_bsr, Jc: vfpi_contacts, tape, grad_v, grad_l
                        grad_phi, grad_mu, opts: vfpi_opts, stats, stream) -> int:
     return load().vfpi_step_backward(ctx, ctypes.byref(A), ctypes.byref(Jc), tape, grad_v, grad_lambda, grad_b,
                                      grad_A_val, grad_phi, grad_mu, ctypes.byref(opts), stats, stream)
+
+
+def vfpi_timing_enable(ctx, on: bool) -> None:
+    check(load().vfpi_timing_enable(ctx, int(bool(on))), "vfpi_timing_enable")
+
+
+def vfpi_timing_read(ctx):
+    """(setup_ms, solve_ms) of the last timed call (waits for its events)."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    check(load().vfpi_timing_read(ctx, ctypes.byref(a), ctypes.byref(b)), "vfpi_timing_read")
+    return a.value, b.value

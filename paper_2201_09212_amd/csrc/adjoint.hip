@@ -50,9 +50,7 @@ struct AdjArgs {
   double tol;
   const int32_t* flags;
   vfpi_stats* stats;
-  double* red;
-  int32_t* ired;
-  uint32_t* sync;
+  uint64_t* slots;
 };
 
 // y = D_P^T x for the contact's branch; *dmu = (dP/dmu)^T x.
@@ -96,7 +94,7 @@ VFPI_DEV void gt_node(const AdjArgs& a, int m, const double u[3], double out[3])
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
   __shared__ double s_red[NW];
-  __shared__ int s_ired[NW];
+  int seq = 0;
   const int G = gridDim.x;
   const int b = blockIdx.x;
   const int lb = xcd_logical_block(b, G);
@@ -146,10 +144,10 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
       }
       for (int r = 0; r < 3; ++r) {
         a.E[3 * i + r] = e[r];
-        a.S[1][3 * i + r] = a.w[3 * i + r] * e[r];
+        stv<true>(a.S[1] + 3 * i + r, a.w[3 * i + r] * e[r]);
       }
     });
-    grid_barrier(a.sync, G);
+    grid_barrier(a.slots, G, lb, ++seq, s_red);
   }
   // phase B: g~ = g_v - e + A p; u0 = g~, t0 = G^T u0, s0 = W t0
   for_my_nodes([&](int64_t n0, int cnt) {
@@ -158,7 +156,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
     double Ap[3] = {0.0, 0.0, 0.0};
     if (a.gl) {
       const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
-      spmv_rows3<double>(a.scol, a.sval, a.S[1], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, Ap);
+      spmv_rows3<double, true>(a.scol, a.sval, a.S[1], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, Ap);
     }
     if (!act) return;
     double u[3], t[3];
@@ -168,10 +166,10 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
       a.gt[3 * i + r] = u[r];
       a.U[0][3 * i + r] = u[r];
       a.T[0][3 * i + r] = t[r];
-      a.S[0][3 * i + r] = a.w[3 * i + r] * t[r];
+      stv<true>(a.S[0] + 3 * i + r, a.w[3 * i + r] * t[r]);
     }
   });
-  grid_barrier(a.sync, G);
+  grid_barrier(a.slots, G, lb, ++seq, s_red);
   int cur = 0;
   if (a.max_iters > 0) {
     int l = 0;
@@ -184,7 +182,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         const bool act = lane < cnt;
         const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
         double As[3];
-        spmv_rows3<double>(a.scol, a.sval, a.S[cur], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, As);
+        spmv_rows3<double, true>(a.scol, a.sval, a.S[cur], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, As);
         if (!act) return;
         double un[3], tn[3];
         for (int r = 0; r < 3; ++r) un[r] = a.gt[3 * i + r] + a.T[cur][3 * i + r] - As[r];
@@ -194,13 +192,11 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
           th2 += d * d;
           a.U[nxt][3 * i + r] = un[r];
           a.T[nxt][3 * i + r] = tn[r];
-          a.S[nxt][3 * i + r] = a.w[3 * i + r] * tn[r];
+          stv<true>(a.S[nxt] + 3 * i + r, a.w[3 * i + r] * tn[r]);
         }
       });
       th2 = block_sum(th2, s_red);
-      const int zero[3] = {0, 0, 0};
-      const bool stop = grid_residual_step(a.sync, a.red, a.ired, G, lb, th2, zero, l, a.max_iters, a.fixed, a.tol,
-                                           a.stats, s_red, s_ired);
+      const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
       cur = nxt;
       if (stop) break;
     }
@@ -273,8 +269,8 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
   if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;
   if (N == 0) {
-    vfpi_stats h = {0, VFPI_S_MAXITER, 0.0, 0, 0, 0, 0};
-    VFPI_CHECK_HIP(hipMemcpyAsync(stats, &h, sizeof(h), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_stats_empty, dim3(1), dim3(1), 0, stream, stats);
+    VFPI_CHECK_HIP(hipGetLastError());
     return VFPI_OK;
   }
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -282,7 +278,9 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   double* cpack = static_cast<double*>(ctx->cpack);
   double* w = static_cast<double*>(ctx->w);
 
-  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync);
+  vfpi_mark(ctx, 0, stream);
+  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync,
+                     ctx->slots, stats);
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
@@ -334,28 +332,25 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   aa.tol = opts->tol;
   aa.flags = ctx->flags;
   aa.stats = stats;
-  aa.red = ctx->red;
-  aa.ired = ctx->ired;
-  aa.sync = ctx->sync;
+  aa.slots = ctx->slots;
 
   const int kind = opts->variant & 0xff;
-  const int grid_req = (opts->variant >> 16) & 0xffff;
+  const int grid_req = (opts->variant >> 16) & 0xff;
   constexpr int NW = 4;
   auto kern = k_adjoint<NW>;
   const int threads = 64 * NW;
   const int64_t want = (nch + NW - 1) / NW;
   int64_t g = 1;
-  if (kind != 3) {
-    int per_cu = 0;
-    VFPI_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0));
-    int64_t cap = (int64_t)per_cu * ctx->num_cu;
-    if (cap > kMaxGrid - 1) cap = kMaxGrid - 1;
+  if (kind != 3) {  // at most one workgroup per CU (see gridsync.h)
+    const int64_t cap = ctx->num_cu < kMaxGridSlots ? ctx->num_cu : kMaxGridSlots;
     g = want < cap ? want : cap;
     if (grid_req > 0 && grid_req < g) g = grid_req;
-    if (g < 1) g = 1;
     if (g > 8) g -= g % 8;
+    if (g < 1) g = 1;
   }
   void* params[] = {&aa};
+  vfpi_mark(ctx, 1, stream);
   VFPI_CHECK_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, stream));
+  vfpi_mark(ctx, 2, stream);
   return VFPI_OK;
 }

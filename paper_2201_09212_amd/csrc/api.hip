@@ -16,9 +16,11 @@ hipError_t alloc(T** p, size_t count) {
 
 void release(vfpi_ctx* c) {
   void* ptrs[] = {c->scol, c->sval, c->diag, c->rn2, c->w, c->vbuf, c->cmap, c->cpack,
-                  c->adj, c->red, c->ired, c->sync, c->ctrl, c->flags};
+                  c->adj, c->slots, c->sync, c->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (int k = 0; k < 3; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
 }
 
 }  // namespace
@@ -56,11 +58,10 @@ extern "C" int vfpi_create(vfpi_ctx** out, int32_t max_nodes, int32_t max_nnzb, 
   if (e == hipSuccess) e = alloc(&c->cmap, (size_t)max_nodes);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->cpack), vfpi::kPack * (size_t)max_contacts);
   if (e == hipSuccess) e = alloc(&c->adj, 8 * n);
-  if (e == hipSuccess) e = alloc(&c->red, 4 * (size_t)vfpi::kMaxGrid);
-  if (e == hipSuccess) e = alloc(&c->ired, 4 * (size_t)vfpi::kMaxGrid);
+  if (e == hipSuccess) e = alloc(&c->slots, 2 * (size_t)vfpi::kMaxGridSlots);
   if (e == hipSuccess) e = alloc(&c->sync, (size_t)vfpi::kSyncWords);
-  if (e == hipSuccess) e = alloc(&c->ctrl, 16);
   if (e == hipSuccess) e = alloc(&c->flags, 1 + (size_t)max_envs);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   if (e == hipSuccess) e = hipMemset(c->sync, 0, vfpi::kSyncWords * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(c->flags, 0, (1 + (size_t)max_envs) * sizeof(int32_t));
   if (e != hipSuccess) {
@@ -85,6 +86,22 @@ extern "C" int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts) {
   if (n_nodes < 0 || n_contacts < 0) return VFPI_E_SHAPE;
   const int64_t raw = 48 * (int64_t)n_nodes + 28 * (int64_t)n_contacts;
   return (raw + 255) / 256 * 256;
+}
+
+extern "C" int vfpi_timing_enable(vfpi_ctx* c, int32_t on) {
+  if (!c) return VFPI_E_NULL;
+  c->timing = on ? 1 : 0;
+  c->timed_calls = 0;
+  return VFPI_OK;
+}
+
+extern "C" int vfpi_timing_read(vfpi_ctx* c, float* setup_ms, float* solve_ms) {
+  if (!c || !setup_ms || !solve_ms) return VFPI_E_NULL;
+  if (!c->timing || c->timed_calls == 0) return VFPI_E_OPTS;
+  VFPI_CHECK_HIP(hipEventSynchronize(c->ev[2]));
+  VFPI_CHECK_HIP(hipEventElapsedTime(setup_ms, c->ev[0], c->ev[1]));
+  VFPI_CHECK_HIP(hipEventElapsedTime(solve_ms, c->ev[1], c->ev[2]));
+  return VFPI_OK;
 }
 
 extern "C" const char* vfpi_error_string(int code) {

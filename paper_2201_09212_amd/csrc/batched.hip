@@ -54,7 +54,7 @@ template <int TPN, int NW>
 __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
   __shared__ float s_vs[2][TPN == 3 ? NW : 1][3][64];
   __shared__ double s_red[TPN * NW];
-  __shared__ int s_ired[TPN * NW];
+  __shared__ int s_ired[3 * TPN * NW];
   __shared__ int s_env;
   __shared__ int s_flag;
   __shared__ int s_stop;
@@ -149,10 +149,8 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
         else
           sweep_chunk_node<float>(d, vcur, vnext, n0, cnt, lane, th2, cb);
       }
-      th2 = block_sum(th2, s_red);
-      const int o = block_sum_int(cb[0], s_ired);
-      const int s = block_sum_int(cb[1], s_ired);
-      const int sl = block_sum_int(cb[2], s_ired);
+      block_sum4(th2, cb[0], cb[1], cb[2], s_red, s_ired);
+      const int o = cb[0], s = cb[1], sl = cb[2];
       if (threadIdx.x == 0) {
         const double theta = sqrt(th2);
         const bool conv = !a.fixed && theta < a.tol;
@@ -268,7 +266,9 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
 
   const int kind = opts->variant & 0xff;
   const int nw = (opts->variant >> 8) & 0xff;
-  const int grid = (opts->variant >> 16) & 0xffff;
+  const int grid = (opts->variant >> 16) & 0xff;
+  vfpi_mark(ctx, 0, stream);
+  vfpi_mark(ctx, 1, stream);  // setup is fused into the batched kernel
   hipError_t e;
   if (kind == 2) {
     e = (nw >= 2) ? launch_batched<3, 2>(ba, grid, ctx->num_cu, stream)
@@ -281,5 +281,6 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   } else {
     return VFPI_E_OPTS;
   }
+  vfpi_mark(ctx, 2, stream);
   return e == hipSuccess ? VFPI_OK : VFPI_E_HIP;
 }

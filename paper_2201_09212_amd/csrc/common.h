@@ -25,6 +25,7 @@ enum { BR_OPEN = 0, BR_STICK = 1, BR_SLIP = 2 };
 
 constexpr int kWave = 64;
 constexpr int kPack = 12;  // per-contact record: R (9), phi, mu, gamma
+constexpr int kMaxGridSlots = 1024;  // workgroups of a persistent launch (slots per parity)
 
 VFPI_DEV uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -34,6 +35,26 @@ VFPI_DEV int lanes_below(uint64_t mask, int lane) {
 }
 
 VFPI_DEV void set_flag(int32_t* flags, int32_t bit) { atomicOr(flags, bit); }
+
+// Loads / stores of the V-FPI iterate v.  COH = true: agent-scope relaxed
+// atomics, coherent across the XCDs' separate L2 caches without any cache
+// write-back or invalidation, so the persistent kernel's grid barrier needs
+// no fences and the read-only A stays cached between sweeps.
+template <bool COH, class T>
+VFPI_DEV T ldv(const T* p) {
+  if constexpr (COH)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+
+template <bool COH, class T>
+VFPI_DEV void stv(T* p, T x) {
+  if constexpr (COH)
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = x;
+}
 
 template <class T>
 VFPI_DEV bool finite(T x) { return __builtin_isfinite(x); }
@@ -95,57 +116,169 @@ VFPI_DEV void for_each_level(int nk, int lane, Fn&& fn) {
   }
 }
 
-// y_r = sum_blocks A_block[r][:] . x[col]  for r = 0..2  (one lane = one node)
-template <class T>
+// Level masks of a group of U levels starting at k0: mask, active count and
+// the level's offset inside the chunk's block range.
+template <int U>
+VFPI_DEV bool level_group(int k0, int nk, int64_t& off, uint64_t m[U], int cnt[U], int64_t offk[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    m[u] = ballot(k0 + u < nk);
+    cnt[u] = __popcll(m[u]);
+    offk[u] = off;
+    off += cnt[u];
+  }
+  return m[0] != 0;
+}
+
+// y_r = sum_blocks A_block[r][:] . x[col]  for r = 0..2  (one lane = one node).
+// Levels are processed in groups of U: all column indices and block entries
+// of the group are loaded first, then all gathers of x, then the products,
+// so the group's memory latencies overlap instead of chaining level by level.
+// The accumulation order is still level by level.
+template <class T, bool COH = false, int U = 4>
 VFPI_DEV void spmv_rows3(const int32_t* __restrict__ scol, const T* __restrict__ sval,
                          const T* __restrict__ x, int64_t base, int nk, int lane, T acc[3]) {
   acc[0] = acc[1] = acc[2] = T(0);
   int64_t off = 0;
-  for (int k = 0;; ++k) {
-    uint64_t mask = ballot(k < nk);
-    if (mask == 0) break;
-    int cnt = __popcll(mask);
-    if (k < nk) {
-      int pos = lanes_below(mask, lane);
-      int64_t q = base + off;
-      int c = scol[q + pos];
-      const T* a = sval + 9 * q + pos;
-      T x0 = x[3 * (int64_t)c], x1 = x[3 * (int64_t)c + 1], x2 = x[3 * (int64_t)c + 2];
-      T a0 = a[0], a1 = a[cnt], a2 = a[2 * cnt];
-      T a3 = a[3 * cnt], a4 = a[4 * cnt], a5 = a[5 * cnt];
-      T a6 = a[6 * cnt], a7 = a[7 * cnt], a8 = a[8 * cnt];
-      acc[0] += a0 * x0 + a1 * x1 + a2 * x2;
-      acc[1] += a3 * x0 + a4 * x1 + a5 * x2;
-      acc[2] += a6 * x0 + a7 * x1 + a8 * x2;
+  for (int k0 = 0;; k0 += U) {
+    uint64_t m[U];
+    int cnt[U];
+    int64_t offk[U];
+    if (!level_group<U>(k0, nk, off, m, cnt, offk)) break;
+    int c[U];
+    T a[U][9];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = 0;
+      if (k0 + u < nk) {
+        const int pos = lanes_below(m[u], lane);
+        const int64_t q = base + offk[u];
+        c[u] = scol[q + pos];
+        const T* ap = sval + 9 * q + pos;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cnt[u]];
+      }
     }
-    off += cnt;
+    T xs[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u < nk) {
+        const T* xp = x + 3 * (int64_t)c[u];
+        xs[u][0] = ldv<COH>(xp);
+        xs[u][1] = ldv<COH>(xp + 1);
+        xs[u][2] = ldv<COH>(xp + 2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u < nk) {
+        acc[0] += a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2];
+        acc[1] += a[u][3] * xs[u][0] + a[u][4] * xs[u][1] + a[u][5] * xs[u][2];
+        acc[2] += a[u][6] * xs[u][0] + a[u][7] * xs[u][1] + a[u][8] * xs[u][2];
+      }
+    }
   }
 }
 
-// y = sum_blocks A_block[r][:] . x[col] for one row r (one lane = one node row)
-template <class T>
+// y = sum_blocks A_block[r][:] . x[col] for one row r (one lane = one node row),
+// with the same grouped issue order.
+template <class T, bool COH = false, int U = 8>
 VFPI_DEV T spmv_row1(const int32_t* __restrict__ scol, const T* __restrict__ sval,
                      const T* __restrict__ x, int64_t base, int nk, int lane, int r) {
   T acc = T(0);
   int64_t off = 0;
-  for (int k = 0;; ++k) {
-    uint64_t mask = ballot(k < nk);
-    if (mask == 0) break;
-    int cnt = __popcll(mask);
-    if (k < nk) {
-      int pos = lanes_below(mask, lane);
-      int64_t q = base + off;
-      int c = scol[q + pos];
-      const T* a = sval + 9 * q + 3 * r * cnt + pos;
-      T x0 = x[3 * (int64_t)c], x1 = x[3 * (int64_t)c + 1], x2 = x[3 * (int64_t)c + 2];
-      acc += a[0] * x0 + a[cnt] * x1 + a[2 * cnt] * x2;
+  for (int k0 = 0;; k0 += U) {
+    uint64_t m[U];
+    int cnt[U];
+    int64_t offk[U];
+    if (!level_group<U>(k0, nk, off, m, cnt, offk)) break;
+    int c[U];
+    T a[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = 0;
+      if (k0 + u < nk) {
+        const int pos = lanes_below(m[u], lane);
+        const int64_t q = base + offk[u];
+        c[u] = scol[q + pos];
+        const T* ap = sval + 9 * q + (int64_t)3 * r * cnt[u] + pos;
+        a[u][0] = ap[0];
+        a[u][1] = ap[cnt[u]];
+        a[u][2] = ap[2 * (int64_t)cnt[u]];
+      }
     }
-    off += cnt;
+    T xs[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u < nk) {
+        const T* xp = x + 3 * (int64_t)c[u];
+        xs[u][0] = ldv<COH>(xp);
+        xs[u][1] = ldv<COH>(xp + 1);
+        xs[u][2] = ldv<COH>(xp + 2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < nk) acc += a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2];
   }
   return acc;
 }
 
 // ---- reductions ---------------------------------------------------------
+// Fixed-order sum of one double and three ints over a workgroup in one pass.
+VFPI_DEV void block_sum4(double& x, int& a, int& b, int& c, double* red, int* ired) {
+  for (int o = 32; o > 0; o >>= 1) {
+    x += __shfl_xor(x, o, 64);
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[wv] = x;
+    ired[3 * wv] = a;
+    ired[3 * wv + 1] = b;
+    ired[3 * wv + 2] = c;
+  }
+  __syncthreads();
+  x = 0.0;
+  a = b = c = 0;
+  for (int i = 0; i < nw; ++i) {
+    x += red[i];
+    a += ired[3 * i];
+    b += ired[3 * i + 1];
+    c += ired[3 * i + 2];
+  }
+  __syncthreads();
+}
+
+// Workgroup sum of three ints (order-independent), result in every thread.
+VFPI_DEV void block_sum4_int(int& a, int& b, int& c, int* ired) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    ired[3 * wv] = a;
+    ired[3 * wv + 1] = b;
+    ired[3 * wv + 2] = c;
+  }
+  __syncthreads();
+  a = b = c = 0;
+  for (int i = 0; i < nw; ++i) {
+    a += ired[3 * i];
+    b += ired[3 * i + 1];
+    c += ired[3 * i + 2];
+  }
+  __syncthreads();
+}
+
 // Fixed-order sum over a workgroup (deterministic): wave butterfly, then the
 // per-wave totals summed in wave order by thread 0.  Result valid in all
 // threads.  `red` is __shared__ scratch of >= blockDim/64 doubles.

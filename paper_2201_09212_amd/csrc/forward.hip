@@ -11,13 +11,29 @@
 
 namespace vfpi {
 
-__global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t* sync) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n_nodes) cmap[i] = -1;
-  if (i == 0) {
+// Per-call reset: node->contact map, error flags, work-queue word, barrier
+// slots and the stats record (its branch counters are accumulated later).
+__global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t* sync, uint64_t* slots,
+                       vfpi_stats* stats) {
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i < n_nodes; i += stride) cmap[i] = -1;
+  for (int64_t i = i0; i < 2 * kMaxGridSlots; i += stride) slots[i] = 0ull;
+  if (i0 == 0) {
     flags[0] = 0;
     for (int k = 0; k < kSyncWords; ++k) sync[k] = 0u;
+    stats->iters = 0;
+    stats->status = 0;
+    stats->theta = 0.0;
+    stats->n_open = stats->n_stick = stats->n_slip = stats->reserved = 0;
   }
+}
+
+__global__ void k_stats_empty(vfpi_stats* st) {
+  st->iters = 0;
+  st->status = VFPI_S_MAXITER;
+  st->theta = 0.0;
+  st->n_open = st->n_stick = st->n_slip = st->reserved = 0;
 }
 
 template <class T>
@@ -51,34 +67,25 @@ struct GridArgs {
   double tol;
   const int32_t* flags;
   vfpi_stats* stats;
-  double* red;
-  int32_t* ired;
-  uint32_t* sync;
+  uint64_t* slots;
 };
 
-VFPI_DEV void write_stats(vfpi_stats* st, int iters, int status, double theta, int o, int s, int l) {
-  st->iters = iters;
-  st->status = status;
-  st->theta = theta;
-  st->n_open = o;
-  st->n_stick = s;
-  st->n_slip = l;
-  st->reserved = 0;
-}
-
-// Persistent V-FPI kernel.  TPN = threads per node (1: a lane owns a node's
-// three rows; 3: three waves own rows 0/1/2 of the same 64 nodes), NW = chunk
-// slots per workgroup.  Needs a cooperative launch when gridDim.x > 1 (all
-// workgroups resident: they meet once per sweep at the residual barrier).
+// Persistent V-FPI kernel: the whole sweep loop of one step.  TPN = threads
+// per node (1: a lane owns a node's three rows; 3: three waves own rows 0/1/2
+// of the same 64 nodes), NW = chunk slots per workgroup.  With more than one
+// workgroup it needs a cooperative launch of at most one workgroup per CU;
+// the workgroups meet once per sweep in the residual reduction.  A workgroup
+// keeps the same nodes in every sweep, and the iterate moves between
+// workgroups through coherent loads / stores only (see gridsync.h).
 template <int TPN, int NW>
 __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
+  constexpr bool COH = true;
   __shared__ double s_vs[2][TPN == 3 ? NW : 1][3][64];
   __shared__ double s_red[TPN * NW];
-  __shared__ int s_ired[TPN * NW];
+  __shared__ int s_ired[3 * TPN * NW];
 
   const int G = gridDim.x;
-  const int b = blockIdx.x;
-  const int lb = xcd_logical_block(b, G);
+  const int lb = xcd_logical_block(blockIdx.x, G);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int slot = wave / TPN, r = (TPN == 3) ? wave % 3 : 0;
   const int64_t nch = (a.n_nodes + 63) / 64;
@@ -87,44 +94,45 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
 
   const int flags = *a.flags;
   if (flags != 0 || a.max_iters <= 0) {
-    for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_contacts;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_contacts;
          k += (int64_t)G * blockDim.x)
       a.d.lambda[k] = 0.0;
-    if (b == 0 && threadIdx.x == 0)
-      write_stats(a.stats, 0, flags ? flags : VFPI_S_MAXITER, INFINITY, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.stats->iters = 0;
+      a.stats->status = flags ? flags : VFPI_S_MAXITER;
+      a.stats->theta = INFINITY;
+    }
     return;
   }
 
   double* vcur = a.v_user;
   double* vnext = a.v_alt;
-  int l = 0;
-  for (;;) {
-    ++l;
+  int cb[3] = {0, 0, 0};
+  for (int l = 1;; ++l) {
     double th2 = 0.0;
-    int cb[3] = {0, 0, 0};
+    cb[0] = cb[1] = cb[2] = 0;
     for (int p = 0; p < passes; ++p) {
       const int64_t c = c0 + (int64_t)p * NW + slot;
       const int64_t n0 = c * 64;
       const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
       if (TPN == 3)
-        sweep_chunk_row<double>(a.d, vcur, vnext, n0, cnt, lane, r, s_vs[p & 1][TPN == 3 ? slot : 0], th2, cb);
+        sweep_chunk_row<double, COH, (64 * TPN * NW >= 960 ? 4 : 8)>(a.d, vcur, vnext, n0, cnt, lane, r,
+                                                                      s_vs[p & 1][TPN == 3 ? slot : 0], th2, cb);
       else
-        sweep_chunk_node<double>(a.d, vcur, vnext, n0, cnt, lane, th2, cb);
+        sweep_chunk_node<double, COH, (64 * TPN * NW >= 960 ? 2 : 4)>(a.d, vcur, vnext, n0, cnt, lane, th2, cb);
     }
     th2 = block_sum(th2, s_red);
-    int cnt3[3];
-    cnt3[0] = block_sum_int(cb[0], s_ired);
-    cnt3[1] = block_sum_int(cb[1], s_ired);
-    cnt3[2] = block_sum_int(cb[2], s_ired);
-    const bool stop = grid_residual_step(a.sync, a.red, a.ired, G, lb, th2, cnt3, l, a.max_iters, a.fixed, a.tol,
-                                         a.stats, s_red, s_ired);
+    const bool stop =
+        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
     double* t = vcur;
     vcur = vnext;
     vnext = t;
     if (stop) break;
   }
+  block_sum4_int(cb[0], cb[1], cb[2], s_ired);
+  add_counts(a.stats, cb[0], cb[1], cb[2]);
   // The final iterate is in vcur.  Each thread copies only entries it wrote
-  // itself in the last sweep, so no further barrier is needed.
+  // itself in the last sweep, so no further synchronization is needed.
   if (vcur != a.v_user || a.tape_v) {
     for (int p = 0; p < passes; ++p) {
       const int64_t c = c0 + (int64_t)p * NW + slot;
@@ -133,7 +141,7 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
       if (lane < cnt) {
         const int64_t i = n0 + lane;
         for (int rr = (TPN == 3 ? r : 0); rr < (TPN == 3 ? r + 1 : 3); ++rr) {
-          const double x = vcur[3 * i + rr];
+          const double x = ldv<COH>(vcur + 3 * i + rr);
           if (vcur != a.v_user) a.v_user[3 * i + rr] = x;
           if (a.tape_v) a.tape_v[3 * i + rr] = x;
         }
@@ -151,41 +159,59 @@ namespace {
 struct Variant {
   int kind;   // 1: grid TPN=1, 2: grid TPN=3, 3: single workgroup TPN=1, 4: single workgroup TPN=3
   int nw;     // chunk slots per workgroup
-  int grid;   // workgroups (0 = auto)
+  int grid;   // workgroup cap (0 = one per CU)
 };
 
 Variant decode_variant(int32_t v, int32_t n_nodes) {
   Variant x;
   x.kind = v & 0xff;
   x.nw = (v >> 8) & 0xff;
-  x.grid = (v >> 16) & 0xffff;
-  if (x.kind == 0) x.kind = (n_nodes <= 1024) ? 3 : 2;
-  if (x.nw == 0) x.nw = (x.kind == 3) ? 16 : (x.kind == 4 ? 5 : (x.kind == 1 ? 4 : 1));
+  x.grid = (v >> 16) & 0xff;
+  if (x.kind == 0) x.kind = (n_nodes <= 1024) ? 3 : 1;
+  if (x.nw == 0) x.nw = (x.kind == 3) ? 16 : (x.kind == 4 ? 5 : (x.kind == 1 ? 2 : 1));
   return x;
 }
 
+// Cooperative launch of at most one workgroup per CU (capped by the number of
+// chunk groups and the caller's cap); the grid is a multiple of 8 above 8 so
+// the XCD-aware numbering is exact.
 template <int TPN, int NW>
 hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool single, hipStream_t st) {
   auto kern = k_vfpi_grid<TPN, NW>;
   const int threads = 64 * TPN * NW;
-  const int64_t nch = (n_nodes + 63) / 64;
-  const int64_t want = (nch + NW - 1) / NW;
   if (single) {
     hipLaunchKernelGGL(kern, dim3(1), dim3(threads), 0, st, ga);
     return hipGetLastError();
   }
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
-  if (e != hipSuccess) return e;
-  int64_t cap = (int64_t)per_cu * num_cu;
-  if (cap > kMaxGrid - 1) cap = kMaxGrid - 1;
-  int64_t g = want < cap ? want : cap;
+  const int64_t nch = (n_nodes + 63) / 64;
+  int64_t g = (nch + NW - 1) / NW;
+  int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
+  if (g > cap) g = cap;
   if (grid_req > 0 && grid_req < g) g = grid_req;
+  if (g > 8) g -= g % 8;
   if (g < 1) g = 1;
-  if (g > 8) g -= g % 8;  // keep the XCD-aware numbering exact
   GridArgs arg = ga;
   void* params[] = {&arg};
   return hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, st);
+}
+
+hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int N, hipStream_t stream) {
+  switch (vr.kind) {
+    case 1:
+      return (vr.nw <= 1)   ? launch_grid<1, 1>(ga, vr.grid, num_cu, N, false, stream)
+             : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, num_cu, N, false, stream)
+                            : launch_grid<1, 4>(ga, vr.grid, num_cu, N, false, stream);
+    case 2:
+      return (vr.nw <= 1) ? launch_grid<3, 1>(ga, vr.grid, num_cu, N, false, stream)
+                          : launch_grid<3, 2>(ga, vr.grid, num_cu, N, false, stream);
+    case 3:
+      return (vr.nw <= 4) ? launch_grid<1, 4>(ga, 1, num_cu, N, true, stream)
+                          : launch_grid<1, 16>(ga, 1, num_cu, N, true, stream);
+    case 4:
+      return launch_grid<3, 5>(ga, 1, num_cu, N, true, stream);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -204,8 +230,8 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;  // a row with two blocks: D-contacts
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
   if (N == 0) {
-    vfpi_stats h = {0, VFPI_S_MAXITER, 0.0, 0, 0, 0, 0};
-    VFPI_CHECK_HIP(hipMemcpyAsync(stats, &h, sizeof(h), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_stats_empty, dim3(1), dim3(1), 0, stream, stats);
+    VFPI_CHECK_HIP(hipGetLastError());
     return VFPI_OK;
   }
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -215,7 +241,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   double* cpack = static_cast<double*>(ctx->cpack);
   double* w = static_cast<double*>(ctx->w);
 
-  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync);
+  vfpi_mark(ctx, 0, stream);
+  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync,
+                     ctx->slots, stats);
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
@@ -255,31 +283,12 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.tol = opts->tol;
   ga.flags = ctx->flags;
   ga.stats = stats;
-  ga.red = ctx->red;
-  ga.ired = ctx->ired;
-  ga.sync = ctx->sync;
+  ga.slots = ctx->slots;
 
   Variant vr = decode_variant(opts->variant, N);
-  hipError_t e;
-  switch (vr.kind) {
-    case 1:
-      e = (vr.nw <= 1) ? launch_grid<1, 1>(ga, vr.grid, ctx->num_cu, N, false, stream)
-        : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, ctx->num_cu, N, false, stream)
-                       : launch_grid<1, 4>(ga, vr.grid, ctx->num_cu, N, false, stream);
-      break;
-    case 2:
-      e = (vr.nw <= 1) ? launch_grid<3, 1>(ga, vr.grid, ctx->num_cu, N, false, stream)
-                       : launch_grid<3, 2>(ga, vr.grid, ctx->num_cu, N, false, stream);
-      break;
-    case 3:
-      e = (vr.nw <= 4) ? launch_grid<1, 4>(ga, 1, ctx->num_cu, N, true, stream)
-                       : launch_grid<1, 16>(ga, 1, ctx->num_cu, N, true, stream);
-      break;
-    case 4:
-      e = launch_grid<3, 5>(ga, 1, ctx->num_cu, N, true, stream);
-      break;
-    default:
-      return VFPI_E_OPTS;
-  }
+  if (vr.kind < 1 || vr.kind > 4) return VFPI_E_OPTS;
+  vfpi_mark(ctx, 1, stream);
+  hipError_t e = launch_variant(vr, ga, ctx->num_cu, N, stream);
+  vfpi_mark(ctx, 2, stream);
   return e == hipSuccess ? VFPI_OK : VFPI_E_HIP;
 }

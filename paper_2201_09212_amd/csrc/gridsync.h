@@ -1,103 +1,104 @@
-// Grid-wide barriers for the persistent kernels (cooperative launch: every
-// workgroup is resident).  One counter + generation word pair in device
-// memory; agent-scope acquire/release atomics make the other XCDs' writes
-// visible (on gfx950 they emit the L2 write-back / invalidate).
+// Grid-wide synchronization for the persistent kernels (cooperative launch,
+// at most one workgroup per CU, so every workgroup is resident).
+//
+// Everything that crosses workgroups (the iterate, the partial sums) moves
+// through agent-scope relaxed atomics, which are coherent across the XCDs'
+// separate L2 caches by themselves; no cache write-back or invalidation is
+// issued, so the read-only A stays cached between sweeps.
+//
+// Barrier + residual reduction without read-modify-write atomics: for its
+// k-th synchronization a workgroup first drains its own stores, then
+// publishes its partial sum in slot[k & 1][lb] with a tag derived from k in
+// the 8 low mantissa bits (the partial keeps 44 significant bits).  Every
+// workgroup polls all G slots of that parity (one slot per thread, in
+// parallel) until each carries the tag, and sums them in slot order: every
+// workgroup gets the same bits, hence the same convergence decision, without
+// a broadcast step.  Double-buffering by parity is enough: a workgroup can
+// only overwrite a slot of parity k & 1 at synchronization k + 2, after every
+// workgroup has published for k + 1, i.e. finished polling for k.  Slots
+// start at tag 0, which no synchronization uses.
 #pragma once
 
 #include "common.h"
 
 namespace vfpi {
 
-// Residual reduction + convergence test of Alg. 1 (theta < tol or l = l_max).
-// Every thread of every workgroup calls.  `th2` and `cnt` are this
-// workgroup's totals, valid in thread 0.  The last workgroup to arrive sums
-// all partials in workgroup-index order (deterministic: the result does not
-// depend on which workgroup arrives last), writes the stats when stopping,
-// and releases the others.  Returns the common stop decision.
-VFPI_DEV bool grid_residual_step(uint32_t* sync, double* red, int32_t* ired, int G, int lb, double th2,
-                                 const int cnt[3], int l, int max_iters, int fixed, double tol, vfpi_stats* stats,
-                                 double* s_red, int* s_ired) {
-  __shared__ int s_last;
-  __shared__ unsigned s_gen;
-  __shared__ int s_stop;
-  auto decide = [&](double tot, int o, int s, int sl) {
-    const double theta = sqrt(tot);
-    const bool conv = !fixed && theta < tol;
-    const bool stop = conv || l >= max_iters;
-    if (stop) {
-      stats->iters = l;
-      stats->status = conv ? VFPI_S_CONVERGED : VFPI_S_MAXITER;
-      stats->theta = theta;
-      stats->n_open = o;
-      stats->n_stick = s;
-      stats->n_slip = sl;
-      stats->reserved = 0;
-    }
-    return stop;
-  };
-  if (G == 1) {
-    if (threadIdx.x == 0) s_stop = decide(th2, cnt[0], cnt[1], cnt[2]);
-  } else {
-    if (threadIdx.x == 0) {
-      red[lb] = th2;
-      ired[3 * lb] = cnt[0];
-      ired[3 * lb + 1] = cnt[1];
-      ired[3 * lb + 2] = cnt[2];
-      const unsigned gen = __hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned old = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      s_gen = gen;
-      s_last = (old == (unsigned)G - 1u);
-    }
-    __syncthreads();
-    if (s_last) {
-      double acc = 0.0;
-      int io = 0, is = 0, il = 0;
-      for (int k = threadIdx.x; k < G; k += blockDim.x) {
-        acc += __hip_atomic_load(red + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        io += __hip_atomic_load(ired + 3 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        is += __hip_atomic_load(ired + 3 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        il += __hip_atomic_load(ired + 3 * k + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      acc = block_sum(acc, s_red);
-      io = block_sum_int(io, s_ired);
-      is = block_sum_int(is, s_ired);
-      il = block_sum_int(il, s_ired);
-      if (threadIdx.x == 0) {
-        const bool stop = decide(acc, io, is, il);
-        s_stop = stop;
-        __hip_atomic_store(red + G, stop ? 1.0 : 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(sync + 1, s_gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    } else if (threadIdx.x == 0) {
-      while (__hip_atomic_load(sync + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == s_gen)
-        __builtin_amdgcn_s_sleep(1);
-      s_stop = __hip_atomic_load(red + G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0.0;
-    }
+template <class T>
+VFPI_DEV T ld_relaxed(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+VFPI_DEV void st_relaxed(T* p, T x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Drain this thread's outstanding memory operations (vector and scalar).
+VFPI_DEV void drain() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+VFPI_DEV unsigned sync_tag(int seq) { return (unsigned)(seq % 255) + 1u; }
+
+VFPI_DEV uint64_t tagged(double x, unsigned tag) {
+  return (__builtin_bit_cast(uint64_t, x) & ~0xffull) | tag;
+}
+VFPI_DEV double untag(uint64_t b) { return __builtin_bit_cast(double, b & ~0xffull); }
+
+// Synchronization number `seq` (1, 2, ... in the same order in every
+// workgroup).  `x` is this workgroup's partial (valid in thread 0).  Returns
+// the fixed-order sum of all workgroups' partials in every thread.
+VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, double* s_red) {
+  const unsigned tag = sync_tag(seq);
+  uint64_t* sl = slots + (seq & 1) * (int64_t)kMaxGridSlots;
+  drain();
+  __syncthreads();
+  if (threadIdx.x == 0) st_relaxed(sl + lb, tagged(x, tag));
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < G; k += blockDim.x) {
+    uint64_t b;
+    while (((b = ld_relaxed(sl + k)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
+    acc += untag(b);
   }
-  __syncthreads();
-  const bool stop = s_stop != 0;
-  __syncthreads();
+  return block_sum(acc, s_red);
+}
+
+// Residual reduction + convergence test of Alg. 1 (theta < tol or l = l_max).
+// Every thread of every workgroup calls with the same seq.  `th2` is this
+// workgroup's partial (valid in thread 0).  Workgroup 0 writes iters,
+// status and theta of the stopping sweep.
+VFPI_DEV bool grid_residual_step(uint64_t* slots, int G, int lb, int seq, double th2, int l, int max_iters,
+                                 int fixed, double tol, vfpi_stats* stats, double* s_red) {
+  const double tot = (G == 1) ? th2 : grid_sum(slots, G, lb, seq, th2, s_red);
+  const double theta = sqrt(tot);
+  const bool conv = !fixed && theta < tol;
+  const bool stop = conv || l >= max_iters;
+  if (stop && lb == 0 && threadIdx.x == 0) {
+    stats->iters = l;
+    stats->status = conv ? VFPI_S_CONVERGED : VFPI_S_MAXITER;
+    stats->theta = theta;
+  }
   return stop;
 }
 
-// Plain grid barrier (all writes before it visible to all workgroups after it).
-VFPI_DEV void grid_barrier(uint32_t* sync, int G) {
-  __shared__ unsigned s_gen2;
-  __syncthreads();
-  if (G > 1 && threadIdx.x == 0) {
-    const unsigned gen = __hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned old = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_gen2 = gen;
-    if (old == (unsigned)G - 1u) {
-      __hip_atomic_store(sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(sync + 1, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      while (__hip_atomic_load(sync + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == s_gen2)
-        __builtin_amdgcn_s_sleep(1);
-    }
+// Plain grid barrier: every write before it is visible to every workgroup
+// after it (through coherent loads).
+VFPI_DEV void grid_barrier(uint64_t* slots, int G, int lb, int seq, double* s_red) {
+  if (G == 1) {
+    __syncthreads();
+    return;
   }
-  __syncthreads();
+  (void)grid_sum(slots, G, lb, seq, 0.0, s_red);
+}
+
+// Branch counts of the final sweep: integer atomics, so the totals do not
+// depend on the order (the counters are zeroed before the launch).
+VFPI_DEV void add_counts(vfpi_stats* st, int o, int s, int sl) {
+  if (threadIdx.x == 0) {
+    if (o) atomicAdd(&st->n_open, o);
+    if (s) atomicAdd(&st->n_stick, s);
+    if (sl) atomicAdd(&st->n_slip, sl);
+  }
 }
 
 // Workgroup numbering that gives each XCD one contiguous range of work

@@ -14,11 +14,10 @@
 
 namespace vfpi {
 
-constexpr int kMaxGrid = 4096;   // upper bound on persistent workgroups
-constexpr int kSyncWords = 64;   // barrier counter, generation, queue, ...
+constexpr int kSyncWords = 64;
 
 // Words of ctx->sync
-enum { SY_COUNT = 0, SY_GEN = 1, SY_QUEUE = 2 };
+enum { SY_QUEUE = 2 };
 
 }  // namespace vfpi
 
@@ -35,13 +34,22 @@ struct vfpi_ctx {
   int32_t* cmap = nullptr;     // [max_nodes] node -> contact (-1: none)
   void* cpack = nullptr;       // [12 max_contacts] R, phi, mu, gamma per contact
   double* adj = nullptr;       // [7 * 3 max_nodes] adjoint vectors
-  double* red = nullptr;       // [4 * kMaxGrid] per-workgroup partial sums
-  int32_t* ired = nullptr;     // [4 * kMaxGrid] per-workgroup partial counts
-  uint32_t* sync = nullptr;    // [kSyncWords]
-  double* ctrl = nullptr;      // [16] broadcast scalars (theta^2, stop flag, ...)
+  uint64_t* slots = nullptr;   // [2 * kMaxGridSlots] tagged per-workgroup partial sums
+  uint32_t* sync = nullptr;    // [kSyncWords] work-queue counter of the batched kernel
   int32_t* flags = nullptr;    // [1 + max_envs] device-detected data errors
   int32_t stats_nodes = -1;    // N for which diag/rn2 hold valid row sums (W reuse)
+  int32_t timing = 0;          // record events around setup / solve
+  int32_t timed_calls = 0;     // calls recorded since enabling
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
+
+// Event marks for the timing aid (no-ops unless enabled).
+inline void vfpi_mark(vfpi_ctx* c, int k, hipStream_t s) {
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[k], s);
+    if (k == 2) c->timed_calls++;
+  }
+}
 
 // Tape layout (bytes from the start): w[n] f64, v[n] f64, lambda*[3nc] f64, branch[nc] i32
 struct TapeView {

@@ -49,7 +49,7 @@ VFPI_DEV int contact_step(const T* __restrict__ pk, T vs0, T vs1, T vs2, int pro
 }
 
 // Thread = node (all three rows).  Every lane of the wave calls; cnt may be 0.
-template <class T>
+template <class T, bool COH = false, int U = 4>
 VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur, T* __restrict__ vnext,
                                int64_t n0, int cnt, int lane, double& th2, int cb[3]) {
   const int64_t i = n0 + lane;
@@ -57,12 +57,12 @@ VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur
   const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
   const int64_t base = cnt > 0 ? a.row_ptr[n0] : 0;  // idle slots may lie past the end
   T Av[3];
-  spmv_rows3<T>(a.scol, a.sval, vcur, base, nk, lane, Av);
+  spmv_rows3<T, COH, U>(a.scol, a.sval, vcur, base, nk, lane, Av);
   if (!act) return;
   T v[3], vs[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    v[r] = vcur[3 * i + r];
+    v[r] = ldv<COH>(vcur + 3 * i + r);
     vs[r] = v[r] - a.w[3 * i + r] * (Av[r] - a.b[3 * i + r]);
   }
   T vn[3] = {vs[0], vs[1], vs[2]};
@@ -83,7 +83,7 @@ VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    vnext[3 * i + r] = vn[r];
+    stv<COH>(vnext + 3 * i + r, vn[r]);
     double d = (double)(vn[r] - v[r]);
     th2 += d * d;
   }
@@ -92,17 +92,17 @@ VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur
 // Thread = one row r of a node; the three rows of a chunk are three waves of
 // the same workgroup that swap v* through LDS (double-buffered by pass parity
 // so one barrier per pass suffices).  Every thread of the workgroup calls.
-template <class T>
+template <class T, bool COH = false, int U = 8>
 VFPI_DEV void sweep_chunk_row(const SweepData<T>& a, const T* __restrict__ vcur, T* __restrict__ vnext,
                               int64_t n0, int cnt, int lane, int r, T (*s_vs)[64], double& th2, int cb[3]) {
   const int64_t i = n0 + lane;
   const bool act = lane < cnt;
   const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
   const int64_t base = cnt > 0 ? a.row_ptr[n0] : 0;  // idle slots may lie past the end
-  const T Av = spmv_row1<T>(a.scol, a.sval, vcur, base, nk, lane, r);
+  const T Av = spmv_row1<T, COH, U>(a.scol, a.sval, vcur, base, nk, lane, r);
   T v = T(0), vs = T(0);
   if (act) {
-    v = vcur[3 * i + r];
+    v = ldv<COH>(vcur + 3 * i + r);
     vs = v - a.w[3 * i + r] * (Av - a.b[3 * i + r]);
     s_vs[r][lane] = vs;
   }
@@ -123,7 +123,7 @@ VFPI_DEV void sweep_chunk_row(const SweepData<T>& a, const T* __restrict__ vcur,
       cb[br] += 1;
     }
   }
-  vnext[3 * i + r] = vn;
+  stv<COH>(vnext + 3 * i + r, vn);
   double d = (double)(vn - v);
   th2 += d * d;
 }

@@ -1,0 +1,106 @@
+"""FP64 HIP adjoint (vfpi_step_backward) vs the FP64 oracle adjoint at a
+converged forward step, and vs central finite differences of the HIP
+forward itself (bar 1e-4 relative; the oracle comparison is held to 1e-7)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_09212_amd as vf
+import scenes
+from oracle.adjoint import adjoint as oracle_adjoint
+from paper_2201_09212_amd import _abi
+from tests.gpu_util import rel, say, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_fwd_bwd(p, gv, gl=None, tol=1e-14, want_A=True, variant=0):
+    s = vf.Solver(p.n_nodes, p.nnzb, max(p.n_contacts, 1))
+    A, Jc, b, v = upload(p)
+    tape = s.tape(p.n_nodes, p.n_contacts)
+    lam, st = s.step(A, b, Jc, v, tape=tape, max_iters=200000, tol=tol)
+    gvt = torch.as_tensor(gv, device="cuda")
+    glt = None if gl is None else torch.as_tensor(gl, device="cuda")
+    g = s.step_backward(A, Jc, tape, gvt, glt, want_A=want_A, max_iters=200000, tol=1e-13, variant=variant)
+    torch.cuda.synchronize()
+    out = {k: (t.cpu().numpy() if isinstance(t, torch.Tensor) and k != "stats" else t) for k, t in g.items()}
+    out["fwd_stats"] = vf.read_stats(st)[0]
+    out["bwd_stats"] = vf.read_stats(g["stats"])[0]
+    out["v"] = v.cpu().numpy()
+    out["lam"] = lam.cpu().numpy()
+    return out
+
+
+def _cases():
+    sc, x, v = scenes.cloth_cfg1(0)
+    yield "cloth10", sc.assemble(x, v)
+    for n, nc, seed in [(14, 7, 0), (70, 40, 1), (200, 90, 2)]:
+        yield f"random{n}", scenes.random_problem(n, nc, seed, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+
+
+@pytest.mark.parametrize("with_glam", [False, True])
+@pytest.mark.parametrize("name,p", list(_cases()))
+def test_adjoint_matches_oracle(name, p, with_glam):
+    g = np.random.default_rng(3)
+    gv = g.normal(size=p.n)
+    gl = g.normal(size=3 * p.n_contacts) if with_glam else None
+    out = gpu_fwd_bwd(p, gv, gl)
+    fwd = oracle.vfpi(p, max_iters=200000, tol=1e-14)
+    ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
+    assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
+    assert out["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, out["bwd_stats"]
+    errs = {k: rel(out[k], ref[k]) for k in ("b", "A", "phi", "mu")}
+    say(f"  {name} glam={with_glam}: fwd {out['fwd_stats']['iters']} bwd {out['bwd_stats']['iters']} sweeps, {errs}")
+    for k, e in errs.items():
+        assert e <= 1e-7, (k, e)
+
+
+def test_adjoint_vs_central_differences_of_gpu_forward():
+    p = scenes.random_problem(40, 18, 5, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+    g = np.random.default_rng(4)
+    gv = g.normal(size=p.n)
+    out = gpu_fwd_bwd(p, gv)
+    s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
+
+    def loss(q):
+        A, Jc, b, v = upload(q)
+        lam, st = s.step(A, b, Jc, v, max_iters=200000, tol=1e-14)
+        torch.cuda.synchronize()
+        return float(gv @ v.cpu().numpy())
+
+    eps = 1e-6
+    checked = 0
+    for k in g.choice(p.n, 8, replace=False):
+        e = np.zeros(p.n)
+        e[k] = eps
+        fd = (loss(scenes.Problem(**{**p.__dict__, "b": p.b + e})) - loss(scenes.Problem(**{**p.__dict__, "b": p.b - e}))) / (2 * eps)
+        assert abs(fd - out["b"][k]) <= 1e-4 * max(1.0, abs(fd)), (k, fd, out["b"][k])
+        checked += 1
+    for m in range(p.n_contacts):
+        for name in ("phi", "mu"):
+            e = np.zeros(p.n_contacts)
+            e[m] = eps
+            base = getattr(p, name)
+            fd = (loss(scenes.Problem(**{**p.__dict__, name: base + e})) -
+                  loss(scenes.Problem(**{**p.__dict__, name: base - e}))) / (2 * eps)
+            assert abs(fd - out[name][m]) <= 1e-4 * max(1.0, abs(fd)), (name, m, fd, out[name][m])
+            checked += 1
+    say(f"  central differences checked: {checked}")
+
+
+def test_adjoint_grid_and_single_workgroup_agree():
+    sc, x, v = scenes.cloth_cfg5_scene(0)
+    x[:, 2] = np.random.default_rng(1).uniform(-5e-4, 4e-3, size=x.shape[0])
+    p = sc.assemble(x, v)
+    gv = np.random.default_rng(2).normal(size=p.n)
+    a = gpu_fwd_bwd(p, gv, tol=1e-13)
+    b = gpu_fwd_bwd(p, gv, tol=1e-13, variant=3)
+    for k in ("b", "phi", "mu"):
+        assert rel(a[k], b[k]) <= 1e-10
+    fwd = oracle.vfpi(p, max_iters=200000, tol=1e-13)
+    ref = oracle_adjoint(p, fwd, gv, tol=1e-14)
+    errs = {k: rel(a[k], ref[k]) for k in ("b", "A", "phi", "mu")}
+    say(f"  cloth64 adjoint: fwd {a['fwd_stats']['iters']} bwd {a['bwd_stats']['iters']} sweeps, {errs}")
+    for k, e in errs.items():
+        assert e <= 1e-6, (k, e)

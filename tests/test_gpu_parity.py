@@ -25,6 +25,8 @@ VARIANTS = {
     "grid_row2": 2 | (2 << 8),
     "grid_node4_cap8": 1 | (4 << 8) | (8 << 16),
     "grid_row1_cap16": 2 | (16 << 16),
+    "grid_row2_cap8": 2 | (2 << 8) | (8 << 16),
+    "grid_node2_cap3": 1 | (2 << 8) | (3 << 16),
 }
 
 CASES = [(1, 1), (5, 0), (5, 5), (63, 20), (64, 64), (65, 30), (130, 77), (700, 300)]
@@ -86,14 +88,14 @@ def test_cloth10_fixed_and_converged():
 def test_cloth128_full_size():
     sc, x, v = scenes.cloth_cfg2(0)
     p = sc.assemble(x, v)
-    for variant in (0, 1 | (4 << 8), 2 | (2 << 8)):
+    for variant in (0, 1 | (4 << 8), 2 | (2 << 8), 2, 1 | (1 << 8)):
         _compare(p, 50, variant)
 
 
 def test_fem_full_size():
     sc, x, v = scenes.fem_cfg3(0)
     p = sc.assemble(x, v)
-    for variant in (0, 1 | (4 << 8)):
+    for variant in (0, 1 | (4 << 8), 2, 1 | (2 << 8)):
         _compare(p, 20, variant)
 
 
