@@ -76,7 +76,11 @@ def plain_bench(args, torch, vf, scenes):
     stats = vf.new_stats(1, dev)
     s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
     L = args.sweeps
-    opt = dict(max_iters=L, fixed_iters=True, variant=args.variant)
+    variant = args.variant
+    if variant == 0:
+        from paper_2201_09212_amd import autotune
+        variant = autotune.best_step_variant(s, A, b, Jc, vv, lam, stats)
+    opt = dict(max_iters=L, fixed_iters=True, variant=variant)
     for _ in range(args.warmup):
         s.step(A, b, Jc, vv, lam, stats=stats, **opt)
     torch.cuda.synchronize()
@@ -114,11 +118,142 @@ def plain_bench(args, torch, vf, scenes):
         "setup_ms": setup_avg,
         "solve_ms": solve_avg,
         "sweep_us": solve_avg * 1e3 / L,
+        "variant": variant,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_vfpi_grid (persistent sweep loop)",
                      "bytes_per_launch": per_sweep * L},
     }
+
+
+def batched_bench(args, torch, vf, scenes):
+    """2048 cloth environments (side 8..48), FP32 with FP64 residual, one
+    persistent launch per step captured in a HIP graph, largest-first queue."""
+    import numpy as np
+    envs = [sc.assemble(x, v) for sc, x, v in scenes.cloth_cfg4_envs(args.seed)]
+    batch = scenes.concat_problems(envs)
+    p = batch.problem
+    dev = torch.device("cuda", 0)
+    A = vf.bsr_from_arrays(p.n_nodes, p.row_ptr, p.col_idx, p.val, dtype=torch.float32, device=dev)
+    crp, ccol, cval = p.jc_bsr()
+    Jc = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, dtype=torch.float32, device=dev)
+    b = torch.as_tensor(p.b, device=dev).float()
+    v = torch.as_tensor(p.v0, device=dev).float()
+    no = torch.as_tensor(batch.env_node_off, device=dev)
+    co = torch.as_tensor(batch.env_con_off, device=dev)
+    order = torch.as_tensor(np.argsort([-e.nnzb for e in envs]).astype(np.int32), device=dev)
+    lam = torch.empty(3 * p.n_contacts, dtype=torch.float32, device=dev)
+    stats = vf.new_stats(batch.n_env, dev)
+    s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts, batch.n_env)
+    L = args.sweeps
+    variant = args.batched_variant
+    if variant == 0:
+        from paper_2201_09212_amd import autotune
+        variant = autotune.best_batched_variant(s, batch, A, b, Jc, v, lam, stats, no, co, order, L)
+    opt = dict(max_iters=L, fixed_iters=True, variant=variant)
+    run = lambda: s.step_batched(batch.n_env, no, co, A, b, Jc, v, lam, env_order=order, stats=stats, **opt)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    # kernel duration from the library's own events (eager launches)
+    vf.vfpi_timing_enable(s.ctx, True)
+    kms = []
+    for _ in range(max(3, args.steps // 4)):
+        run()
+        kms.append(vf.vfpi_timing_read(s.ctx)[1])
+    vf.vfpi_timing_enable(s.ctx, False)
+    # timed region: graph replays
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = vf.read_stats(stats)
+    assert all(x["iters"] == L for x in st)
+    s.close()
+    kavg = sum(kms) / len(kms)
+    per_sweep = sum(sweep_bytes(e.n_nodes, e.nnzb, e.n_contacts, 4) for e in envs)
+    achieved = per_sweep * L / (kavg * 1e-3) / 1e9
+    return {"value": batch.n_env / (ms * 1e-3), "unit": "env-step/s", "ms_per_step": ms, "n_env": batch.n_env,
+            "n_nodes": p.n_nodes, "nnzb": p.nnzb, "n_contacts": p.n_contacts, "sweeps_per_step": L,
+            "dtype": "f32 (f64 residual)", "graph": True, "variant": variant, "kernel_ms": kavg,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBPS, "traffic": load_traffic("batched2048", L),
+                         "kernel": "k_vfpi_batched (persistent, one launch per step)",
+                         "bytes_per_launch": per_sweep * L},
+            "vs_plain_contact_iters_per_s": p.n_contacts * L / (ms * 1e-3)}
+
+
+def adjoint_bench(args, torch, vf, scenes):
+    """64x64 cloth: one converged step (tol 1e-13) forward with tape and its
+    adjoint (kernel times), and a 100-step rollout with gradient (checkpoint
+    every 10 steps) against the same rollout without gradient."""
+    from paper_2201_09212_amd.autograd import rollout
+    from scenes.cloth_torch import TorchCloth
+    dev = torch.device("cuda", 0)
+    sc, x0, v0 = scenes.cloth_cfg5_scene(args.seed)
+    tc = TorchCloth(sc, dev)
+    s = vf.Solver(sc.n_nodes, tc.nnzb, sc.n_nodes)
+    # single landed step: kernel times of forward and backward
+    import numpy as np
+    xl = x0.copy()
+    xl[:, 2] = np.random.default_rng(args.seed).uniform(-5e-4, 4e-3, size=xl.shape[0])
+    vl = v0.copy()
+    vl[:, 2] -= 0.6
+    p = sc.assemble(xl, vl)
+    A = vf.bsr_from_arrays(p.n_nodes, p.row_ptr, p.col_idx, p.val, device=dev)
+    crp, ccol, cval = p.jc_bsr()
+    Jc = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, device=dev)
+    b = torch.as_tensor(p.b, device=dev)
+    gv = torch.as_tensor(np.random.default_rng(1).normal(size=p.n), device=dev)
+    tape = s.tape(p.n_nodes, p.n_contacts)
+    vf.vfpi_timing_enable(s.ctx, True)
+    fwd, bwd, fit, bit = [], [], 0, 0
+    for _ in range(5):
+        v = torch.as_tensor(p.v0, device=dev).clone()
+        lam, st = s.step(A, b, Jc, v, tape=tape, max_iters=100000, tol=1e-13)
+        fwd.append(vf.vfpi_timing_read(s.ctx)[1])
+        g = s.step_backward(A, Jc, tape, gv, max_iters=100000, tol=1e-13, want_A=True)
+        bwd.append(vf.vfpi_timing_read(s.ctx)[1])
+        fit, bit = vf.read_stats(st)[0]["iters"], vf.read_stats(g["stats"])[0]["iters"]
+    vf.vfpi_timing_enable(s.ctx, False)
+    # rollout
+    x0t = torch.as_tensor(x0, device=dev)
+    v0t = torch.as_tensor(v0, device=dev)
+    target = x0t.clone()
+    kk = torch.tensor(1e3, device=dev, dtype=torch.float64, requires_grad=True)
+    mu = torch.full((sc.n_nodes,), 0.5, device=dev, dtype=torch.float64, requires_grad=True)
+    steps = args.rollout_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        rollout(tc, s, x0t, v0t, (kk, mu), steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xN, _ = rollout(tc, s, x0t, v0t, (kk, mu), steps, checkpoint_every=10)
+    ((xN - target) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    s.close()
+    fm, bm = sorted(fwd)[len(fwd) // 2], sorted(bwd)[len(bwd) // 2]
+    return {"step_fwd_ms": fm, "step_bwd_ms": bm, "bwd_over_fwd_step": bm / fm, "fwd_sweeps": fit,
+            "bwd_sweeps": bit, "n_contacts": p.n_contacts, "rollout_steps": steps,
+            "rollout_fwd_s": t_fwd, "rollout_fwd_bwd_s": t_fb,
+            "bwd_over_fwd_rollout": (t_fb - t_fwd) / t_fwd,
+            "workload": "cloth64x64 on plane, FP64, converged to 1e-13, checkpoint every 10 steps"}
 
 
 def cpu_baseline(args, p, oracle_mod, budget_s):
@@ -146,6 +281,10 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batched-variant", type=int, default=0)
+    ap.add_argument("--rollout-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it", file=sys.stderr)
@@ -165,10 +304,14 @@ def main():
         "config": {"workload": "cloth128x128_16spheres_fp64", "n_nodes": p.n_nodes, "dof": p.n, "nnzb": p.nnzb,
                    "n_contacts": p.n_contacts, "sweeps_per_step": args.sweeps, "parallelism": "single GPU"},
         "hbm_gbps": r["roofline"]["achieved"], "hbm_frac": r["roofline"]["frac"],
-        "sweep_us": r["sweep_us"], "setup_ms": r["setup_ms"], "solve_ms": r["solve_ms"],
+        "sweep_us": r["sweep_us"], "setup_ms": r["setup_ms"], "solve_ms": r["solve_ms"], "variant": r["variant"],
         "dof_iters_per_s": p.n * args.sweeps * args.steps / (r["ms_per_step"] * args.steps * 1e-3),
         "roofline": r["roofline"],
     }
+    if not args.no_batched:
+        out["batched"] = batched_bench(args, torch, vf, scenes)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench(args, torch, vf, scenes)
     if not args.no_cpu:
         import oracle
         out["cpu_baseline"] = cpu_baseline(args, p, oracle, args.cpu_seconds)

@@ -1,0 +1,110 @@
+"""Launch-variant autotuner for the plain and batched V-FPI kernels.
+
+A variant is the ``vfpi_opts.variant`` word: ``kind | slots << 8 | cap << 16``
+where kind 1 = one lane per node, 2 = three lanes (rows) per node, 3/4 = the
+same on a single workgroup; ``slots`` = 64-node chunks per workgroup pass;
+``cap`` = workgroup limit (0 = library default).  The tuner times each
+candidate on the caller's own problem with the library's HIP events (a short
+fixed number of sweeps), keeps the fastest, and caches the choice in a JSON
+file keyed by the problem's shape so later runs skip the search.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import _abi
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.environ.get("VFPI_TUNE_CACHE", os.path.join(HERE, "tuned_variants.json"))
+
+PLAIN_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 2 | (1 << 8), 2 | (2 << 8),
+                    1 | (2 << 8) | (128 << 16), 1 | (4 << 8) | (128 << 16), 3 | (16 << 8), 3 | (4 << 8)]
+BATCHED_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 1 | (8 << 8), 2 | (1 << 8), 2 | (2 << 8)]
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    try:
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def _time(solver, call, reps=3):
+    _abi.vfpi_timing_enable(solver.ctx, True)
+    try:
+        call()  # warm-up
+        best = None
+        for _ in range(reps):
+            call()
+            ms = _abi.vfpi_timing_read(solver.ctx)[1]
+            best = ms if best is None else min(best, ms)
+        return best
+    finally:
+        _abi.vfpi_timing_enable(solver.ctx, False)
+
+
+def _search(key, candidates, call_for, log):
+    cache = _load()
+    if key in cache:
+        return int(cache[key]["variant"])
+    results = {}
+    for var in candidates:
+        try:
+            results[var] = _time(call_for.solver, lambda: call_for(var))
+        except _abi.VfpiError:
+            continue
+        if log:
+            log(f"autotune {key}: variant {var:#x} {results[var]:.3f} ms")
+    best = min(results, key=results.get)
+    cache[key] = {"variant": best, "ms": results[best], "candidates": {hex(k): v for k, v in results.items()}}
+    _store(cache)
+    return best
+
+
+def best_step_variant(solver, A, b, Jc, v, lam, stats, sweeps=20, log=None):
+    """Fastest vfpi_step variant for this problem shape (FP64)."""
+    key = f"step/N{A.n_nodes}/nnzb{A.nnzb}/nc{Jc.n_contacts}"
+    v0 = v.clone()
+
+    def call(var):
+        v.copy_(v0)
+        solver.step(A, b, Jc, v, lam, stats=stats, max_iters=sweeps, fixed_iters=True, variant=var)
+
+    call.solver = solver
+    best = _search(key, PLAIN_CANDIDATES, call, log)
+    v.copy_(v0)
+    torch.cuda.synchronize()
+    return best
+
+
+def best_batched_variant(solver, batch, A, b, Jc, v, lam, stats, env_node_off, env_con_off, env_order, sweeps,
+                         log=None):
+    """Fastest vfpi_step_batched variant for this batch shape (FP32)."""
+    key = f"batched/E{batch.n_env}/N{A.n_nodes}/nnzb{A.nnzb}/nc{Jc.n_contacts}"
+    v0 = v.clone()
+    short = max(5, min(sweeps, 20))
+
+    def call(var):
+        v.copy_(v0)
+        solver.step_batched(batch.n_env, env_node_off, env_con_off, A, b, Jc, v, lam, env_order=env_order,
+                            stats=stats, max_iters=short, fixed_iters=True, variant=var)
+
+    call.solver = solver
+    best = _search(key, BATCHED_CANDIDATES, call, log)
+    v.copy_(v0)
+    torch.cuda.synchronize()
+    return best

@@ -122,3 +122,40 @@ def test_full_batch_sampled():
     worst = _check_envs(batch, v, lam, st, L, envs_idx=sample)
     say(f"  full batch: {batch.n_env} envs, {batch.problem.n_nodes} nodes, sample sizes {min(sizes)}-{max(sizes)}, "
         f"worst rel {worst:.2e}")
+
+
+def test_graph_capture_replays_match_eager():
+    """The batched step captured in a HIP graph (torch.cuda.CUDAGraph) gives
+    the eager result on every replay, with eager work and syncs in between."""
+    envs = _envs_small()
+    batch = scenes.concat_problems(envs)
+    dev = torch.device("cuda", 0)
+    p = batch.problem
+    s = vf.Solver(p.n_nodes, p.nnzb, max(p.n_contacts, 1), batch.n_env)
+    A, Jc, b, v, no, co = _upload_batch(batch, dev)
+    v0 = v.clone()
+    lam = torch.empty(3 * p.n_contacts, dtype=torch.float32, device=dev)
+    st = vf.new_stats(batch.n_env, dev)
+    opt = dict(max_iters=15, fixed_iters=True)
+    s.step_batched(batch.n_env, no, co, A, b, Jc, v, lam, stats=st, **opt)
+    torch.cuda.synchronize()
+    ref_v, ref_l = v.clone(), lam.clone()
+    g = torch.cuda.CUDAGraph()
+    v.copy_(v0)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        s.step_batched(batch.n_env, no, co, A, b, Jc, v, lam, stats=st, **opt)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        s.step_batched(batch.n_env, no, co, A, b, Jc, v, lam, stats=st, **opt)
+    for rep in range(4):
+        v.copy_(v0)          # eager work between replays
+        lam.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(v, ref_v) and torch.equal(lam, ref_l), rep
+        assert all(x["iters"] == 15 for x in vf.read_stats(st))
