@@ -285,6 +285,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-variant", type=int, default=0)
     ap.add_argument("--rollout-steps", type=int, default=100)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it", file=sys.stderr)
@@ -315,6 +317,13 @@ def main():
     if not args.no_cpu:
         import oracle
         out["cpu_baseline"] = cpu_baseline(args, p, oracle, args.cpu_seconds)
+    if args.copy_calibration:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read_per_copy": 1 << 30, "bytes_written_per_copy": 1 << 30, "copies": 3}
     print(json.dumps(out), flush=True)
 
 

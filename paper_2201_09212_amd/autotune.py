@@ -2,7 +2,8 @@
 
 A variant is the ``vfpi_opts.variant`` word: ``kind | slots << 8 | cap << 16``
 where kind 1 = one lane per node, 2 = three lanes (rows) per node, 3/4 = the
-same on a single workgroup; ``slots`` = 64-node chunks per workgroup pass;
+same on a single workgroup, 5 = one lane per node with A's row kept in
+registers for the whole step (one chunk pass per workgroup); ``slots`` = 64-node chunks per workgroup pass;
 ``cap`` = workgroup limit (0 = library default).  The tuner times each
 candidate on the caller's own problem with the library's HIP events (a short
 fixed number of sweeps), keeps the fastest, and caches the choice in a JSON
@@ -12,6 +13,7 @@ from __future__ import annotations
 
 import json
 import os
+import zlib
 
 import torch
 
@@ -21,7 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("VFPI_TUNE_CACHE", os.path.join(HERE, "tuned_variants.json"))
 
 PLAIN_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 2 | (1 << 8), 2 | (2 << 8),
-                    1 | (2 << 8) | (128 << 16), 1 | (4 << 8) | (128 << 16), 3 | (16 << 8), 3 | (4 << 8)]
+                    1 | (2 << 8) | (128 << 16), 1 | (4 << 8) | (128 << 16), 3 | (16 << 8), 3 | (4 << 8),
+                    5 | (1 << 8), 5 | (2 << 8), 5 | (4 << 8), 5 | (8 << 8)]
 BATCHED_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 1 | (8 << 8), 2 | (1 << 8), 2 | (2 << 8)]
 
 
@@ -58,6 +61,7 @@ def _time(solver, call, reps=3):
 
 
 def _search(key, candidates, call_for, log):
+    key = f"{key}/cand{zlib.crc32(repr(candidates).encode()) & 0xffff:04x}"
     cache = _load()
     if key in cache:
         return int(cache[key]["variant"])

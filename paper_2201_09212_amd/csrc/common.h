@@ -130,17 +130,18 @@ VFPI_DEV bool level_group(int k0, int nk, int64_t& off, uint64_t m[U], int cnt[U
   return m[0] != 0;
 }
 
-// y_r = sum_blocks A_block[r][:] . x[col]  for r = 0..2  (one lane = one node).
-// Levels are processed in groups of U: all column indices and block entries
-// of the group are loaded first, then all gathers of x, then the products,
-// so the group's memory latencies overlap instead of chaining level by level.
-// The accumulation order is still level by level.
+// y_r += sum_blocks A_block[r][:] . x[col]  for r = 0..2  (one lane = one node),
+// over the levels k >= k_start (whose blocks start at offset off_start of the
+// chunk's block range).  Levels are processed in groups of U: all column
+// indices and block entries of the group are loaded first, then all gathers
+// of x, then the products, so the group's memory latencies overlap instead of
+// chaining level by level.  The accumulation order is level by level.
 template <class T, bool COH = false, int U = 4>
-VFPI_DEV void spmv_rows3(const int32_t* __restrict__ scol, const T* __restrict__ sval,
-                         const T* __restrict__ x, int64_t base, int nk, int lane, T acc[3]) {
-  acc[0] = acc[1] = acc[2] = T(0);
-  int64_t off = 0;
-  for (int k0 = 0;; k0 += U) {
+VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restrict__ sval,
+                              const T* __restrict__ x, int64_t base, int nk, int lane, int k_start,
+                              int64_t off_start, T acc[3]) {
+  int64_t off = off_start;
+  for (int k0 = k_start;; k0 += U) {
     uint64_t m[U];
     int cnt[U];
     int64_t offk[U];
@@ -178,6 +179,13 @@ VFPI_DEV void spmv_rows3(const int32_t* __restrict__ scol, const T* __restrict__
       }
     }
   }
+}
+
+template <class T, bool COH = false, int U = 4>
+VFPI_DEV void spmv_rows3(const int32_t* __restrict__ scol, const T* __restrict__ sval,
+                         const T* __restrict__ x, int64_t base, int nk, int lane, T acc[3]) {
+  acc[0] = acc[1] = acc[2] = T(0);
+  spmv_rows3_from<T, COH, U>(scol, sval, x, base, nk, lane, 0, 0, acc);
 }
 
 // y = sum_blocks A_block[r][:] . x[col] for one row r (one lane = one node row),

@@ -150,6 +150,164 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
   }
 }
 
+
+// Register-resident variant of the persistent kernel (variant kind 5): each
+// workgroup owns at most NW chunks (one pass), so a lane keeps, for the whole
+// step, its node's first KC block levels of A (values and columns), b, W, the
+// contact record, and its own iterate v^l (which it wrote itself).  A sweep
+// gathers the neighbours' v (coherent loads when COH, i.e. more than one
+// workgroup), streams the levels beyond KC, runs the epilogue, and writes
+// v^{l+1} through LDS so every wave stores whole cache lines; lambda and the
+// tape are written once, after the last sweep.  Same arithmetic and order as
+// the streaming kernel.
+template <int NW, int KC, bool COH>
+__global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
+  __shared__ double s_red[NW];
+  __shared__ int s_ired[3 * NW];
+  __shared__ double s_out[NW][192];
+  const int G = gridDim.x;
+  const int lb = xcd_logical_block(blockIdx.x, G);
+  const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nch = (a.n_nodes + 63) / 64;
+  const int64_t c0 = lb * nch / G, c1 = (lb + 1) * nch / G;
+  const int64_t c = c0 + slot;
+  const int64_t n0 = c * 64;
+  const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+  const int64_t i = n0 + lane;
+  const bool act = lane < cnt;
+
+  const int flags = *a.flags;
+  if (flags != 0 || a.max_iters <= 0) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_contacts;
+         k += (int64_t)G * blockDim.x)
+      a.d.lambda[k] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.stats->iters = 0;
+      a.stats->status = flags ? flags : VFPI_S_MAXITER;
+      a.stats->theta = INFINITY;
+    }
+    return;
+  }
+  const SweepData<double>& d = a.d;
+  const int nk = act ? d.row_ptr[i + 1] - d.row_ptr[i] : 0;
+  const int64_t base = cnt > 0 ? d.row_ptr[n0] : 0;
+  int col[KC];
+  double av[KC][9];
+  int64_t off = 0;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const uint64_t m = ballot(k < nk);
+    const int ck = __popcll(m);
+    col[k] = 0;
+    if (k < nk) {
+      const int pos = lanes_below(m, lane);
+      const int64_t q = base + off;
+      col[k] = d.scol[q + pos];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) av[k][e] = d.sval[9 * q + (int64_t)e * ck + pos];
+    }
+    off += ck;
+  }
+  const int64_t off_tail = off;
+  double bi[3] = {0.0, 0.0, 0.0}, wi[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
+  int m = -1;
+  ContactRec<double> cr{};
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      bi[r] = d.b[3 * i + r];
+      wi[r] = d.w[3 * i + r];
+      vo[r] = a.v_user[3 * i + r];
+    }
+    m = d.cmap[i];
+    if (m >= 0) cr = load_contact<double>(d.cpack + kPack * (int64_t)m);
+  }
+  double lam[3] = {0.0, 0.0, 0.0}, ls[3] = {0.0, 0.0, 0.0};
+  int br = BR_OPEN;
+  double* vcur = a.v_user;
+  double* vnext = a.v_alt;
+  for (int l = 1;; ++l) {
+    double xs[KC][3];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      if (k < nk) {
+        const double* xp = vcur + 3 * (int64_t)col[k];
+        xs[k][0] = ldv<COH>(xp);
+        xs[k][1] = ldv<COH>(xp + 1);
+        xs[k][2] = ldv<COH>(xp + 2);
+      }
+    }
+    double Av[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      if (k < nk) {
+        Av[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
+        Av[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
+        Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
+      }
+    }
+    spmv_rows3_from<double, COH, (NW >= 8 ? 2 : 4)>(d.scol, d.sval, vcur, base, nk, lane, KC, off_tail, Av);
+    double th2 = 0.0;
+    double vn[3] = {0.0, 0.0, 0.0};
+    if (act) {
+      double vs[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        vs[r] = vo[r] - wi[r] * (Av[r] - bi[r]);
+        vn[r] = vs[r];
+      }
+      if (m >= 0) {
+        br = contact_solve<double>(cr, vs[0], vs[1], vs[2], d.proj, lam, ls);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
+          vn[r] = vs[r] + wi[r] * F;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double dd = vn[r] - vo[r];
+        th2 += dd * dd;
+        s_out[slot][3 * lane + r] = vn[r];
+      }
+    }
+    __syncthreads();
+    // the wave's 3*cnt values are contiguous in v: store them as whole lines
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int e = lane + 64 * j;
+      if (e < 3 * cnt) stv<COH>(vnext + 3 * n0 + e, s_out[slot][e]);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) vo[r] = vn[r];
+    th2 = block_sum(th2, s_red);
+    const bool stop = grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+    double* t = vcur;
+    vcur = vnext;
+    vnext = t;
+    if (stop) break;
+  }
+  int cb[3] = {0, 0, 0};
+  if (act && m >= 0) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      d.lambda[3 * (int64_t)m + r] = lam[r];
+      if (d.tape_lamstar) d.tape_lamstar[3 * (int64_t)m + r] = ls[r];
+    }
+    if (d.tape_branch) d.tape_branch[m] = br;
+    cb[br] = 1;
+  }
+  block_sum4_int(cb[0], cb[1], cb[2], s_ired);
+  add_counts(a.stats, cb[0], cb[1], cb[2]);
+  if (act && (vcur != a.v_user || a.tape_v)) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (vcur != a.v_user) a.v_user[3 * i + r] = vo[r];
+      if (a.tape_v) a.tape_v[3 * i + r] = vo[r];
+    }
+  }
+}
+
 }  // namespace vfpi
 
 using namespace vfpi;
@@ -195,8 +353,35 @@ hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
   return hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, st);
 }
 
+// Register-resident kernel: one pass per workgroup, so the grid must cover
+// every chunk with at most NW chunks per workgroup; refused (invalid value)
+// when the problem needs more than one workgroup per CU.
+template <int NW, int KC>
+hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, hipStream_t st) {
+  const int64_t nch = (n_nodes + 63) / 64;
+  int64_t g = (nch + NW - 1) / NW;
+  const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
+  if (grid_req > 0 && grid_req > g) g = grid_req < nch ? grid_req : nch;
+  if (g > 8 && g % 8 != 0) g += 8 - g % 8;  // round up: every workgroup still gets <= NW chunks
+  if (g > nch) g = nch;
+  if (g > cap) return hipErrorInvalidValue;
+  GridArgs arg = ga;
+  void* params[] = {&arg};
+  if (g == 1) {  // one workgroup: plain loads, no cooperative launch needed
+    hipLaunchKernelGGL((k_vfpi_regs<NW, KC, false>), dim3(1), dim3(64 * NW), 0, st, ga);
+    return hipGetLastError();
+  }
+  return hipLaunchCooperativeKernel((const void*)k_vfpi_regs<NW, KC, true>, dim3((unsigned)g), dim3(64 * NW), params,
+                                    0, st);
+}
+
 hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int N, hipStream_t stream) {
   switch (vr.kind) {
+    case 5:
+      return (vr.nw <= 1)   ? launch_regs<1, 9>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 2) ? launch_regs<2, 9>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 4) ? launch_regs<4, 9>(ga, vr.grid, num_cu, N, stream)
+                            : launch_regs<8, 4>(ga, vr.grid, num_cu, N, stream);
     case 1:
       return (vr.nw <= 1)   ? launch_grid<1, 1>(ga, vr.grid, num_cu, N, false, stream)
              : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, num_cu, N, false, stream)
@@ -286,9 +471,10 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.slots = ctx->slots;
 
   Variant vr = decode_variant(opts->variant, N);
-  if (vr.kind < 1 || vr.kind > 4) return VFPI_E_OPTS;
+  if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
   vfpi_mark(ctx, 1, stream);
   hipError_t e = launch_variant(vr, ga, ctx->num_cu, N, stream);
+  if (e == hipErrorInvalidValue) return VFPI_E_OPTS;
   vfpi_mark(ctx, 2, stream);
   return e == hipSuccess ? VFPI_OK : VFPI_E_HIP;
 }

@@ -28,14 +28,30 @@ struct SweepData {
   int proj;
 };
 
+// One contact's packed record: R (row 0 = normal), phi, mu, gamma.
+template <class T>
+struct ContactRec {
+  T R[9];
+  T phi, mu, g;
+};
+
+template <class T>
+VFPI_DEV ContactRec<T> load_contact(const T* __restrict__ pk) {
+  ContactRec<T> c;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) c.R[e] = pk[e];
+  c.phi = pk[9];
+  c.mu = pk[10];
+  c.g = pk[11];
+  return c;
+}
+
 // Contact step for one S-contact given v* of its node; returns the branch and
 // writes lambda (and lambda* for the tape).
 template <class T>
-VFPI_DEV int contact_step(const T* __restrict__ pk, T vs0, T vs1, T vs2, int proj, T lam[3], T ls[3]) {
-  T R[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) R[e] = pk[e];
-  const T phi = pk[9], mu = pk[10], g = pk[11];
+VFPI_DEV int contact_solve(const ContactRec<T>& cr, T vs0, T vs1, T vs2, int proj, T lam[3], T ls[3]) {
+  const T* R = cr.R;
+  const T phi = cr.phi, mu = cr.mu, g = cr.g;
   const T e0 = R[0] * vs0 + R[1] * vs1 + R[2] * vs2;
   const T e1 = R[3] * vs0 + R[4] * vs1 + R[5] * vs2;
   const T e2 = R[6] * vs0 + R[7] * vs1 + R[8] * vs2;
@@ -46,6 +62,11 @@ VFPI_DEV int contact_step(const T* __restrict__ pk, T vs0, T vs1, T vs2, int pro
   lam[1] = ls[1];
   lam[2] = ls[2];
   return project(proj, lam[0], lam[1], lam[2], mu);
+}
+
+template <class T>
+VFPI_DEV int contact_step(const T* __restrict__ pk, T vs0, T vs1, T vs2, int proj, T lam[3], T ls[3]) {
+  return contact_solve<T>(load_contact<T>(pk), vs0, vs1, vs2, proj, lam, ls);
 }
 
 // Thread = node (all three rows).  Every lane of the wave calls; cnt may be 0.

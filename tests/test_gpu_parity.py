@@ -27,6 +27,11 @@ VARIANTS = {
     "grid_row1_cap16": 2 | (16 << 16),
     "grid_row2_cap8": 2 | (2 << 8) | (8 << 16),
     "grid_node2_cap3": 1 | (2 << 8) | (3 << 16),
+    "regs_node1": 5 | (1 << 8),
+    "regs_node2": 5 | (2 << 8),
+    "regs_node4": 5 | (4 << 8),
+    "regs_node8": 5 | (8 << 8),
+    "regs_node1_grid16": 5 | (1 << 8) | (16 << 16),
 }
 
 CASES = [(1, 1), (5, 0), (5, 5), (63, 20), (64, 64), (65, 30), (130, 77), (700, 300)]
@@ -75,7 +80,7 @@ def test_user_w_and_proximal_parity(mode):
 def test_cloth10_fixed_and_converged():
     sc, x, v = scenes.cloth_cfg1(0)
     p = sc.assemble(x, v)
-    for variant in (0, 3, 4, 2):
+    for variant in (0, 3, 4, 2, 5 | (1 << 8)):
         _compare(p, 50, variant)
     ref = oracle.vfpi(p, max_iters=1000, tol=1e-10)
     v_, lam, st, _ = gpu_step(p, max_iters=1000, tol=1e-10)
@@ -88,14 +93,14 @@ def test_cloth10_fixed_and_converged():
 def test_cloth128_full_size():
     sc, x, v = scenes.cloth_cfg2(0)
     p = sc.assemble(x, v)
-    for variant in (0, 1 | (4 << 8), 2 | (2 << 8), 2, 1 | (1 << 8)):
+    for variant in (0, 1 | (4 << 8), 2 | (2 << 8), 2, 1 | (1 << 8), 5 | (1 << 8), 5 | (2 << 8), 5 | (4 << 8)):
         _compare(p, 50, variant)
 
 
 def test_fem_full_size():
     sc, x, v = scenes.fem_cfg3(0)
     p = sc.assemble(x, v)
-    for variant in (0, 1 | (4 << 8), 2, 1 | (2 << 8)):
+    for variant in (0, 1 | (4 << 8), 2, 1 | (2 << 8), 5 | (8 << 8)):
         _compare(p, 20, variant)
 
 
