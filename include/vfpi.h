@@ -116,7 +116,14 @@ typedef struct {
   double  alpha_user;    /* VFPI_W_USER_SCALAR only                             */
   int32_t reuse_w;       /* 1: keep the row sums a_dd, ||A_d*||^2 of the previous
                             call on this context (W reuse across steps, Sec. IV-C) */
-  int32_t variant;       /* kernel variant, 0 = library default (autotuned)     */
+  int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16;
+                            0 = library default (see paper_2201_09212_amd/autotune.py) */
+  int32_t cheby_ls;      /* 0: off; l_s >= 1: Chebyshev acceleration (Alg. 3):
+                            nu = 1 before sweep l_s, 2/(2 - rho^2) at l_s, then
+                            4/(4 - rho^2 nu); rho = min(theta_l / theta_{l-1}, 1) */
+  double  cheby_u;       /* under-relaxation u of the accelerated update (0 < u <= 1;
+                            0 is read as 1):
+                            v^{l+1} = nu (u (v** - v^l) + v^l - v^{l-1}) + v^{l-1} */
 } vfpi_opts;
 
 /* Written on the device; `stats` points to device memory. */

@@ -15,7 +15,7 @@ hipError_t alloc(T** p, size_t count) {
 }
 
 void release(vfpi_ctx* c) {
-  void* ptrs[] = {c->scol, c->sval, c->diag, c->rn2, c->w, c->vbuf, c->cmap, c->cpack,
+  void* ptrs[] = {c->scol, c->sval, c->diag, c->rn2, c->w, c->vbuf, c->vprev, c->cmap, c->cpack,
                   c->adj, c->slots, c->sync, c->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -33,6 +33,7 @@ int vfpi_check_opts(const vfpi_opts* o, bool batched) {
   if (o->w_mode == VFPI_W_USER_DIAG && !o->w_user) return VFPI_E_NULL;
   if (o->w_mode == VFPI_W_USER_SCALAR && !(o->alpha_user > 0.0)) return VFPI_E_OPTS;
   if (batched && o->w_mode != VFPI_W_FROBENIUS && o->w_mode != VFPI_W_USER_SCALAR) return VFPI_E_UNSUPPORTED;
+  if (o->cheby_ls < 0 || !(o->cheby_u >= 0.0 && o->cheby_u <= 1.0)) return VFPI_E_OPTS;
   return VFPI_OK;
 }
 
@@ -55,6 +56,7 @@ extern "C" int vfpi_create(vfpi_ctx** out, int32_t max_nodes, int32_t max_nnzb, 
   if (e == hipSuccess) e = alloc(&c->rn2, n);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->w), n);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->vbuf), n);
+  if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->vprev), n);
   if (e == hipSuccess) e = alloc(&c->cmap, (size_t)max_nodes);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->cpack), vfpi::kPack * (size_t)max_contacts);
   if (e == hipSuccess) e = alloc(&c->adj, 8 * n);

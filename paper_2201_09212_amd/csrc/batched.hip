@@ -11,6 +11,7 @@
 #include "internal.h"
 #include "setup.h"
 #include "sweep.h"
+#include "gridsync.h"
 
 namespace vfpi {
 
@@ -46,6 +47,9 @@ struct BatchArgs {
   RowsArgs ra;
   vfpi_stats* stats;
   uint32_t* queue;
+  float* vprev;        // Chebyshev v^{l-1} buffer
+  int32_t cheby_ls;    // 0: off
+  double cheby_u;
 };
 
 __global__ void k_reset_queue(uint32_t* q) { *q = 0u; }
@@ -132,6 +136,11 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
     d.tape_lamstar = nullptr;
     d.tape_branch = nullptr;
     d.proj = a.proj;
+    Cheby ch;
+    ch.ls = a.cheby_ls;
+    ch.u = a.cheby_u;
+    d.vprev = ch.ls ? a.vprev : nullptr;
+    d.u = ch.u;
     float* vcur = a.v_user;
     float* vnext = a.v_alt;
     const int passes = (int)((nch + NW - 1) / NW);
@@ -140,6 +149,8 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
       ++l;
       double th2 = 0.0;
       int cb[3] = {0, 0, 0};
+      d.nu = ch.next_nu(l);
+      d.first = (l == 1);
       for (int p = 0; p < passes; ++p) {
         const int64_t c = (int64_t)p * NW + slot;
         const int64_t n0 = n_lo + 64 * c;
@@ -169,6 +180,7 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
       }
       __syncthreads();
       const bool stop = s_stop != 0;
+      if (!stop) ch.observe(sqrt(th2));
       float* t = vcur;
       vcur = vnext;
       vnext = t;
@@ -262,6 +274,9 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   ba.ra.alpha = opts->alpha_user;
   ba.stats = per_env_stats;
   ba.queue = ctx->sync + SY_QUEUE;
+  ba.vprev = static_cast<float*>(ctx->vprev);
+  ba.cheby_ls = opts->cheby_ls;
+  ba.cheby_u = opts->cheby_u == 0.0 ? 1.0 : opts->cheby_u;
   ctx->stats_nodes = N;
 
   const int kind = opts->variant & 0xff;

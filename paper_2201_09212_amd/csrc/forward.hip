@@ -68,6 +68,9 @@ struct GridArgs {
   const int32_t* flags;
   vfpi_stats* stats;
   uint64_t* slots;
+  double* vprev;       // Chebyshev v^{l-1} buffer (streaming kernels)
+  int32_t cheby_ls;    // 0: off
+  double cheby_u;
 };
 
 // Persistent V-FPI kernel: the whole sweep loop of one step.  TPN = threads
@@ -108,26 +111,36 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
   double* vcur = a.v_user;
   double* vnext = a.v_alt;
   int cb[3] = {0, 0, 0};
+  SweepData<double> d = a.d;
+  Cheby ch;
+  ch.ls = a.cheby_ls;
+  ch.u = a.cheby_u;
+  d.vprev = ch.ls ? a.vprev : nullptr;
+  d.u = ch.u;
   for (int l = 1;; ++l) {
     double th2 = 0.0;
     cb[0] = cb[1] = cb[2] = 0;
+    d.nu = ch.next_nu(l);
+    d.first = (l == 1);
     for (int p = 0; p < passes; ++p) {
       const int64_t c = c0 + (int64_t)p * NW + slot;
       const int64_t n0 = c * 64;
       const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
       if (TPN == 3)
-        sweep_chunk_row<double, COH, (64 * TPN * NW >= 960 ? 4 : 8)>(a.d, vcur, vnext, n0, cnt, lane, r,
+        sweep_chunk_row<double, COH, (64 * TPN * NW >= 960 ? 4 : 8)>(d, vcur, vnext, n0, cnt, lane, r,
                                                                       s_vs[p & 1][TPN == 3 ? slot : 0], th2, cb);
       else
-        sweep_chunk_node<double, COH, (64 * TPN * NW >= 960 ? 2 : 4)>(a.d, vcur, vnext, n0, cnt, lane, th2, cb);
+        sweep_chunk_node<double, COH, (64 * TPN * NW >= 960 ? 2 : 4)>(d, vcur, vnext, n0, cnt, lane, th2, cb);
     }
     th2 = block_sum(th2, s_red);
+    double theta;
     const bool stop =
-        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red, &theta);
     double* t = vcur;
     vcur = vnext;
     vnext = t;
     if (stop) break;
+    ch.observe(theta);
   }
   block_sum4_int(cb[0], cb[1], cb[2], s_ired);
   add_counts(a.stats, cb[0], cb[1], cb[2]);
@@ -223,10 +236,15 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     if (m >= 0) cr = load_contact<double>(d.cpack + kPack * (int64_t)m);
   }
   double lam[3] = {0.0, 0.0, 0.0}, ls[3] = {0.0, 0.0, 0.0};
+  double vp[3] = {vo[0], vo[1], vo[2]};  // v^{l-1} for Chebyshev acceleration (v^0 = v^1)
   int br = BR_OPEN;
   double* vcur = a.v_user;
   double* vnext = a.v_alt;
+  Cheby ch;
+  ch.ls = a.cheby_ls;
+  ch.u = a.cheby_u;
   for (int l = 1;; ++l) {
+    const double nu = ch.next_nu(l);
     double xs[KC][3];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -264,6 +282,14 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
           vn[r] = vs[r] + wi[r] * F;
         }
       }
+      if (ch.ls) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double p = vp[r];
+          vp[r] = vo[r];
+          vn[r] = nu * (ch.u * (vn[r] - vo[r]) + vo[r] - p) + p;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         const double dd = vn[r] - vo[r];
@@ -281,11 +307,14 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) vo[r] = vn[r];
     th2 = block_sum(th2, s_red);
-    const bool stop = grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+    double theta;
+    const bool stop =
+        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red, &theta);
     double* t = vcur;
     vcur = vnext;
     vnext = t;
     if (stop) break;
+    ch.observe(theta);
   }
   int cb[3] = {0, 0, 0};
   if (act && m >= 0) {
@@ -469,6 +498,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.flags = ctx->flags;
   ga.stats = stats;
   ga.slots = ctx->slots;
+  ga.vprev = static_cast<double*>(ctx->vprev);
+  ga.cheby_ls = opts->cheby_ls;
+  ga.cheby_u = opts->cheby_u == 0.0 ? 1.0 : opts->cheby_u;
 
   Variant vr = decode_variant(opts->variant, N);
   if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;

@@ -68,9 +68,10 @@ VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, doub
 // workgroup's partial (valid in thread 0).  Workgroup 0 writes iters,
 // status and theta of the stopping sweep.
 VFPI_DEV bool grid_residual_step(uint64_t* slots, int G, int lb, int seq, double th2, int l, int max_iters,
-                                 int fixed, double tol, vfpi_stats* stats, double* s_red) {
+                                 int fixed, double tol, vfpi_stats* stats, double* s_red, double* theta_out = nullptr) {
   const double tot = (G == 1) ? th2 : grid_sum(slots, G, lb, seq, th2, s_red);
   const double theta = sqrt(tot);
+  if (theta_out) *theta_out = theta;
   const bool conv = !fixed && theta < tol;
   const bool stop = conv || l >= max_iters;
   if (stop && lb == 0 && threadIdx.x == 0) {
@@ -100,6 +101,26 @@ VFPI_DEV void add_counts(vfpi_stats* st, int o, int s, int sl) {
     if (sl) atomicAdd(&st->n_slip, sl);
   }
 }
+
+// Chebyshev acceleration state (Alg. 3), identical in every workgroup because
+// it only depends on the reduced residuals.
+struct Cheby {
+  int ls = 0;            // 0: off
+  double u = 1.0;
+  double nu = 1.0, rho = 0.0, theta_prev = 0.0;
+  // nu_{l+1} used by sweep l
+  VFPI_DEV double next_nu(int l) {
+    if (l < ls) nu = 1.0;
+    else if (l == ls) nu = 2.0 / (2.0 - rho * rho);
+    else nu = 4.0 / (4.0 - rho * rho * nu);
+    return nu;
+  }
+  // after the stop test of sweep l (eq. varrho from the two latest residuals)
+  VFPI_DEV void observe(double theta) {
+    rho = theta_prev > 0.0 ? fmin(theta / theta_prev, 1.0) : 0.0;
+    theta_prev = theta;
+  }
+};
 
 // Workgroup numbering that gives each XCD one contiguous range of work
 // (workgroups are dealt round-robin to the 8 XCDs).

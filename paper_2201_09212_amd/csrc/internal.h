@@ -31,6 +31,7 @@ struct vfpi_ctx {
   double* rn2 = nullptr;       // [3 max_nodes] ||A_d*||^2
   void* w = nullptr;           // [3 max_nodes] step sizes
   void* vbuf = nullptr;        // [3 max_nodes] second buffer of the V-FPI iterate
+  void* vprev = nullptr;       // [3 max_nodes] v^{l-1} for Chebyshev acceleration (node-local)
   int32_t* cmap = nullptr;     // [max_nodes] node -> contact (-1: none)
   void* cpack = nullptr;       // [12 max_contacts] R, phi, mu, gamma per contact
   double* adj = nullptr;       // [7 * 3 max_nodes] adjoint vectors

@@ -26,7 +26,21 @@ struct SweepData {
   double* tape_lamstar;   // nullable (FP64 path only)
   int32_t* tape_branch;   // nullable
   int proj;
+  // Chebyshev acceleration (Alg. 3): v^{l+1} = nu (u (v** - v^l) + v^l - v^{l-1}) + v^{l-1}
+  T* vprev;               // v^{l-1} per DOF, node-local (nullptr: off)
+  double nu, u;
+  int first;              // sweep 1: v^0 = v^1
 };
+
+// Chebyshev update of one DOF (identity when d.vprev is null); keeps v^l as the
+// next sweep's v^{l-1}.
+template <class T>
+VFPI_DEV T cheby_update(const SweepData<T>& a, int64_t k, T vss, T v) {
+  if (!a.vprev) return vss;
+  const T vp = a.first ? v : a.vprev[k];
+  a.vprev[k] = v;
+  return (T)a.nu * ((T)a.u * (vss - v) + v - vp) + vp;
+}
 
 // One contact's packed record: R (row 0 = normal), phi, mu, gamma.
 template <class T>
@@ -104,6 +118,7 @@ VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
+    vn[r] = cheby_update<T>(a, 3 * i + r, vn[r], v[r]);
     stv<COH>(vnext + 3 * i + r, vn[r]);
     double d = (double)(vn[r] - v[r]);
     th2 += d * d;
@@ -144,6 +159,7 @@ VFPI_DEV void sweep_chunk_row(const SweepData<T>& a, const T* __restrict__ vcur,
       cb[br] += 1;
     }
   }
+  vn = cheby_update<T>(a, 3 * i + r, vn, v);
   stv<COH>(vnext + 3 * i + r, vn);
   double d = (double)(vn - v);
   th2 += d * d;
