@@ -124,6 +124,9 @@ typedef struct {
   double  cheby_u;       /* under-relaxation u of the accelerated update (0 < u <= 1;
                             0 is read as 1):
                             v^{l+1} = nu (u (v** - v^l) + v^l - v^{l-1}) + v^{l-1} */
+  double  omega;         /* invertible contact (Sec. III-E, eq. invt): Omega_c = omega I,
+                            the contact step uses gamma_m + omega (omega >= 0; 0 = off).
+                            vfpi_step_backward must get the forward call's value. */
 } vfpi_opts;
 
 /* Written on the device; `stats` points to device memory. */

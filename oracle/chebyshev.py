@@ -36,7 +36,7 @@ from .core import (contact_gamma, contact_jacobian, frobenius_w, project_proxima
 
 
 def vfpi_chebyshev(p, *, max_iters=100, tol=0.0, fixed_iters=False, l_s=10, u=1.0, w_mode="frobenius",
-                   alpha_user=None, projection="strict", history=False, rho_fixed=None):
+                   alpha_user=None, projection="strict", history=False, rho_fixed=None, omega=0.0):
     """``rho_fixed`` replaces the estimate of eq. varrho by a constant (a test
     hook: with the exact spectral radius the classical error bound applies)."""
     A = validate(p)
@@ -49,7 +49,7 @@ def vfpi_chebyshev(p, *, max_iters=100, tol=0.0, fixed_iters=False, l_s=10, u=1.
         w = np.full(p.n, float(alpha_user))
     else:
         raise ValueError(w_mode)
-    gamma = contact_gamma(p, w)
+    gamma = contact_gamma(p, w) + omega
     phi_e1 = np.zeros(3 * nc)
     phi_e1[0::3] = p.phi
     v = p.v0.copy()

@@ -192,7 +192,7 @@ def gershgorin_alpha(A):
 
 
 def vfpi(p, *, max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_user=None,
-         alpha_user=None, projection="strict", stats=None, history=False):
+         alpha_user=None, projection="strict", stats=None, history=False, omega=0.0):
     """Alg. 1 inner loop (the V-FPI) with Alg. 2 as its contact step.
 
     ``w_mode``: "frobenius" (Sec. IV-C.1), "diag" (user W, ``w_user``[n],
@@ -200,6 +200,9 @@ def vfpi(p, *, max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_
     "bb1" / "bb2" (Sec. IV-C.2).  ``stats`` = (a_dd, ||A_d*||^2) reuses the
     row sums of an earlier A (W reuse across steps, Sec. IV-C, last paragraph).
     With ``fixed_iters`` exactly ``max_iters`` sweeps run regardless of ``tol``.
+    ``omega`` > 0 is the invertible contact of Sec. III-E (eq. invt) with
+    Omega_c = omega I: the surrogate problem uses Gamma_c + Omega_c, i.e. the
+    contact step divides by gamma_m + omega.
     """
     A = validate(p)
     J = contact_jacobian(p)
@@ -226,7 +229,7 @@ def vfpi(p, *, max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_
         raise ValueError(w_mode)
     if np.any(w <= 0):
         raise ValueError("W must be positive")
-    gamma = contact_gamma(p, w)
+    gamma = contact_gamma(p, w) + omega
     phi_e1 = np.zeros(3 * nc)
     phi_e1[0::3] = p.phi
     v = p.v0.copy()
@@ -248,7 +251,7 @@ def vfpi(p, *, max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_
             elif w_mode == "bb2" and sz > 0 and zz > 0:
                 alpha = sz / zz
             w = np.full(n, alpha)
-            gamma = contact_gamma(p, w)
+            gamma = contact_gamma(p, w) + omega
         vs = v - w * (Av - p.b)                                   # eq. pgd1
         eta = J @ vs                                              # eq. subp
         lam_star = (-(eta + phi_e1) / np.repeat(gamma, 3)).reshape(nc, 3)   # Alg. 2

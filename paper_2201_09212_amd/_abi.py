@@ -57,7 +57,7 @@ class vfpi_opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("w_mode", ctypes.c_int32), ("projection", ctypes.c_int32), ("w_user", ctypes.c_void_p),
                 ("alpha_user", ctypes.c_double), ("reuse_w", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("cheby_ls", ctypes.c_int32), ("cheby_u", ctypes.c_double)]
+                ("cheby_ls", ctypes.c_int32), ("cheby_u", ctypes.c_double), ("omega", ctypes.c_double)]
 
 
 class vfpi_stats(ctypes.Structure):
@@ -67,7 +67,7 @@ class vfpi_stats(ctypes.Structure):
 
 
 assert ctypes.sizeof(vfpi_stats) == 32
-assert ctypes.sizeof(vfpi_opts) == 64
+assert ctypes.sizeof(vfpi_opts) == 72
 
 _lib = None
 

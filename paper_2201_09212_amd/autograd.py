@@ -58,9 +58,12 @@ DEFAULT_BWD = dict(max_iters=100000, tol=1e-13)
 
 def vfpi_solve(solver, A_val, b, phi, mu, v_warm, row_ptr, col_idx, n_nodes, c_node, R, fwd_opts=None,
                bwd_opts=None):
-    """Differentiable V-FPI step; returns (v, lambda, stats tensor)."""
-    return VfpiStepFn.apply(A_val, b, phi, mu, v_warm, solver, row_ptr, col_idx, n_nodes, c_node, R,
-                            fwd_opts or DEFAULT_FWD, bwd_opts or DEFAULT_BWD)
+    """Differentiable V-FPI step; returns (v, lambda, stats tensor).  The
+    backward pass uses the forward's contact regularization (omega)."""
+    fwd = dict(fwd_opts or DEFAULT_FWD)
+    bwd = dict(bwd_opts or DEFAULT_BWD)
+    bwd["omega"] = fwd.get("omega", 0.0)
+    return VfpiStepFn.apply(A_val, b, phi, mu, v_warm, solver, row_ptr, col_idx, n_nodes, c_node, R, fwd, bwd)
 
 
 def rollout(scene, solver, x0, v0, params, steps, checkpoint_every=10, fwd_opts=None, bwd_opts=None,

@@ -78,15 +78,17 @@ VFPI_DEV void dp_transpose(const double* ls, int br, double mu, const double x[3
   *dmu = n * ht;
 }
 
-// (G^T u)_i for a node: u - R^T D_P^T R u on a contact node (gamma = w_i), u elsewhere.
-VFPI_DEV void gt_node(const AdjArgs& a, int m, const double u[3], double out[3]) {
+// (G^T u)_i for a node: u - R^T D_P^T R (w_i u) / g on a contact node, with g
+// = gamma_m (+ omega), u elsewhere.
+VFPI_DEV void gt_node(const AdjArgs& a, int64_t i, int m, const double u[3], double out[3]) {
   out[0] = u[0];
   out[1] = u[1];
   out[2] = u[2];
   if (m < 0) return;
   const double* R = a.cpack + kPack * (int64_t)m;
+  const double f = a.w[3 * i] / R[11];
   double x[3], y[3], dmu;
-  for (int k = 0; k < 3; ++k) x[k] = R[3 * k] * u[0] + R[3 * k + 1] * u[1] + R[3 * k + 2] * u[2];
+  for (int k = 0; k < 3; ++k) x[k] = (R[3 * k] * u[0] + R[3 * k + 1] * u[1] + R[3 * k + 2] * u[2]) * f;
   dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
   for (int r = 0; r < 3; ++r) out[r] -= R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
 }
@@ -161,7 +163,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
     if (!act) return;
     double u[3], t[3];
     for (int r = 0; r < 3; ++r) u[r] = a.gl ? a.gv[3 * i + r] - a.E[3 * i + r] + Ap[r] : a.gv[3 * i + r];
-    gt_node(a, a.cmap[i], u, t);
+    gt_node(a, i, a.cmap[i], u, t);
     for (int r = 0; r < 3; ++r) {
       a.gt[3 * i + r] = u[r];
       a.U[0][3 * i + r] = u[r];
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         if (!act) return;
         double un[3], tn[3];
         for (int r = 0; r < 3; ++r) un[r] = a.gt[3 * i + r] + a.T[cur][3 * i + r] - As[r];
-        gt_node(a, a.cmap[i], un, tn);
+        gt_node(a, i, a.cmap[i], un, tn);
         for (int r = 0; r < 3; ++r) {
           const double d = un[r] - a.U[cur][3 * i + r];
           th2 += d * d;
@@ -291,6 +293,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   ra.w_mode = VFPI_W_USER_DIAG;
   ra.reuse = false;
   ra.alpha = 0.0;
+  ra.omega = opts->omega;
   const int64_t nch = (N + 63) / 64;
   hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, stream, N, A->row_ptr, A->col_idx,
                      static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), nullptr, nullptr,

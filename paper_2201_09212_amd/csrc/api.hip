@@ -34,6 +34,7 @@ int vfpi_check_opts(const vfpi_opts* o, bool batched) {
   if (o->w_mode == VFPI_W_USER_SCALAR && !(o->alpha_user > 0.0)) return VFPI_E_OPTS;
   if (batched && o->w_mode != VFPI_W_FROBENIUS && o->w_mode != VFPI_W_USER_SCALAR) return VFPI_E_UNSUPPORTED;
   if (o->cheby_ls < 0 || !(o->cheby_u >= 0.0 && o->cheby_u <= 1.0)) return VFPI_E_OPTS;
+  if (!(o->omega >= 0.0) || !__builtin_isfinite(o->omega)) return VFPI_E_OPTS;
   return VFPI_OK;
 }
 

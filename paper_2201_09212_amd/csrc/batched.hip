@@ -272,6 +272,7 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   ba.ra.w_mode = opts->w_mode;
   ba.ra.reuse = opts->reuse_w != 0;
   ba.ra.alpha = opts->alpha_user;
+  ba.ra.omega = opts->omega;
   ba.stats = per_env_stats;
   ba.queue = ctx->sync + SY_QUEUE;
   ba.vprev = static_cast<float*>(ctx->vprev);

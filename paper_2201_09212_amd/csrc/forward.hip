@@ -467,6 +467,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ra.w_mode = opts->w_mode;
   ra.reuse = opts->reuse_w != 0;
   ra.alpha = opts->alpha_user;
+  ra.omega = opts->omega;
   const int64_t nch = (N + 63) / 64;
   hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, stream, N, A->row_ptr, A->col_idx,
                      static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), ctx->diag,

@@ -3,7 +3,8 @@
 //    node, eq. jcnode), build the node -> contact map, pack R, phi, mu;
 //  * block rows of A: copy into the chunk-interleaved layout (see common.h),
 //    accumulate a_dd and ||A_d*||^2, and form the step sizes W (Sec. IV-C.1)
-//    and gamma_m = w_i of Prop. 3.
+//    and gamma_m = w_i of Prop. 3 (plus omega for the invertible contact of
+//    eq. invt, whose Omega_c = omega I is simply added to Gamma_c).
 #pragma once
 
 #include "common.h"
@@ -59,6 +60,7 @@ struct RowsArgs {
   int w_mode;
   bool reuse;
   double alpha;
+  double omega;  // invertible contact: the contact step divides by gamma + omega
 };
 
 // One wave converts one chunk of <= 64 consecutive nodes [n0, n0 + cnt).
@@ -170,7 +172,7 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
     w[3 * i + r] = (T)wr[r];
     if (tape_w) tape_w[3 * i + r] = wr[r];
   }
-  if (m >= 0) cpack[kPack * (int64_t)m + 11] = (T)wr[0];
+  if (m >= 0) cpack[kPack * (int64_t)m + 11] = (T)(wr[0] + ra.omega);
 }
 
 }  // namespace vfpi

@@ -86,10 +86,10 @@ def contacts_from_arrays(row_ptr, col_idx, val, phi, mu, dtype=torch.float64, de
 
 
 def make_opts(max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_user=None, alpha=0.0,
-              projection="strict", reuse_w=False, variant=0, cheby_ls=0, cheby_u=1.0) -> _abi.vfpi_opts:
+              projection="strict", reuse_w=False, variant=0, cheby_ls=0, cheby_u=1.0, omega=0.0) -> _abi.vfpi_opts:
     return _abi.vfpi_opts(int(max_iters), int(bool(fixed_iters)), float(tol), W_MODES[w_mode],
                           PROJECTIONS[projection], _ptr(w_user), float(alpha or 0.0), int(bool(reuse_w)),
-                          int(variant), int(cheby_ls), float(cheby_u))
+                          int(variant), int(cheby_ls), float(cheby_u), float(omega))
 
 
 def new_stats(n=1, device=None):

@@ -31,15 +31,17 @@ def test_iterative_adjoint_matches_dense(seed):
         np.testing.assert_allclose(a[k], d[k], rtol=0, atol=1e-10 * (1 + np.abs(d[k]).max()))
 
 
-def _loss(p, gv, gl):
-    f = _fwd(p)
+def _loss(p, gv, gl, omega=0.0):
+    f = _fwd(p, omega=omega)
     return gv @ f["v"] + gl @ f["lam"].ravel(), f["branch"]
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_adjoint_matches_central_differences(seed):
+@pytest.mark.parametrize("seed,omega", [(0, 0.0), (1, 0.0), (2, 0.0), (0, 0.02), (1, 0.3)])
+def test_adjoint_matches_central_differences(seed, omega):
+    """With omega > 0 (invertible contact, eq. invt) the same adjoint applies
+    with gamma + omega in the contact step."""
     p = _problem(seed)
-    f = _fwd(p)
+    f = _fwd(p, omega=omega)
     g = np.random.default_rng(100 + seed)
     gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
     grad = adjoint(p, f, gv, gl)
@@ -47,8 +49,8 @@ def test_adjoint_matches_central_differences(seed):
     checked = 0
 
     def fd(make):
-        lp, bp = _loss(make(+eps), gv, gl)
-        lm, bm = _loss(make(-eps), gv, gl)
+        lp, bp = _loss(make(+eps), gv, gl, omega)
+        lm, bm = _loss(make(-eps), gv, gl, omega)
         if not (np.array_equal(bp, f["branch"]) and np.array_equal(bm, f["branch"])):
             return None  # the active set changed inside +-eps: not differentiable there
         return (lp - lm) / (2 * eps)

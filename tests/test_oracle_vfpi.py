@@ -206,3 +206,19 @@ def test_zero_iterations_and_empty_contacts():
     r = oracle.vfpi(p, max_iters=0)
     np.testing.assert_array_equal(r["v"], p.v0)
     assert r["iters"] == 0 and r["lam"].shape == (0, 3)
+
+
+@pytest.mark.parametrize("omega", [1e-3, 0.05])
+def test_invertible_contact_recovers_impulse_from_velocity(omega):
+    """Invertible contact (eq. invt, Omega = omega I): at convergence the
+    impulse is a function of the velocity alone, lambda_m =
+    ProjectFC(-(J_m v + phi_m e1) / omega)."""
+    p = scenes.random_problem(40, 16, 9, degree=4.0, phi_scale=0.5, mu_range=(0.1, 0.9))
+    r = oracle.vfpi(p, max_iters=200000, tol=1e-15, omega=omega)
+    u = (contact_jacobian(p) @ r["v"]).reshape(-1, 3)
+    u[:, 0] += p.phi
+    lam_from_v, _ = oracle.project_strict(-u / omega, p.mu)
+    np.testing.assert_allclose(r["lam"], lam_from_v, atol=1e-9 * max(1.0, np.abs(r["lam"]).max()))
+    # and it differs from the exact (omega = 0) model
+    r0 = oracle.vfpi(p, max_iters=200000, tol=1e-15)
+    assert np.abs(r0["v"] - r["v"]).max() > 1e-6 * omega
