@@ -72,6 +72,13 @@ extern "C" {
 #define VFPI_W_USER_SCALAR  2  /* W = opts.alpha_user I                        */
 #define VFPI_W_BB1          3  /* Barzilai-Borwein s's/s'z (Sec. IV-C.2)       */
 #define VFPI_W_BB2          4  /* Barzilai-Borwein s'z/z'z (Sec. IV-C.2)       */
+/* BB modes: W = alpha^l I with alpha^1 = 1/max_d sum_j |a_dj| and, for l >= 2,
+ * s = v^l - v^{l-1}, z = A v^l - A v^{l-1}; alpha is kept when the quotient is
+ * not positive.  vfpi_step only, launch kinds 1 and 3, no Chebyshev
+ * (VFPI_E_UNSUPPORTED otherwise); two grid reductions per sweep.  The tape
+ * of a BB step holds W = alpha I of the last sweep; the adjoint iteration of
+ * vfpi_step_backward contracts only if that alpha is below 2 / lambda_max(A),
+ * which a long BB step need not be (differentiate a FROBENIUS step instead). */
 
 /* ---- ProjectFC (eq. operator) ------------------------------------------ */
 #define VFPI_PROJ_STRICT    0  /* normal clamp + disk projection (default)     */
@@ -163,7 +170,8 @@ int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts);
  *   tape    NULL, or a device buffer of vfpi_tape_bytes(N, n_c) bytes that
  *           receives what vfpi_step_backward needs
  * Errors: VFPI_E_NULL, VFPI_E_SHAPE, VFPI_E_OPTS, VFPI_E_CAPACITY,
- * VFPI_E_UNSUPPORTED (a J_c row with two blocks: D-contacts), VFPI_E_HIP. */
+ * VFPI_E_UNSUPPORTED (a J_c row with two blocks: D-contacts; BB modes with
+ * Chebyshev or with launch kinds other than 1 and 3), VFPI_E_HIP. */
 int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc,
               double* v, double* lambda, const vfpi_opts* opts, vfpi_stats* stats,
               void* tape, hipStream_t stream);

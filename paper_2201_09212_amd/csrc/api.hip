@@ -61,7 +61,7 @@ extern "C" int vfpi_create(vfpi_ctx** out, int32_t max_nodes, int32_t max_nnzb, 
   if (e == hipSuccess) e = alloc(&c->cmap, (size_t)max_nodes);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->cpack), vfpi::kPack * (size_t)max_contacts);
   if (e == hipSuccess) e = alloc(&c->adj, 8 * n);
-  if (e == hipSuccess) e = alloc(&c->slots, 2 * (size_t)vfpi::kMaxGridSlots);
+  if (e == hipSuccess) e = alloc(&c->slots, (size_t)vfpi::kSlotWords);
   if (e == hipSuccess) e = alloc(&c->sync, (size_t)vfpi::kSyncWords);
   if (e == hipSuccess) e = alloc(&c->flags, 1 + (size_t)max_envs);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);

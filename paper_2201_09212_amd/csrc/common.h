@@ -26,6 +26,11 @@ enum { BR_OPEN = 0, BR_STICK = 1, BR_SLIP = 2 };
 constexpr int kWave = 64;
 constexpr int kPack = 12;  // per-contact record: R (9), phi, mu, gamma
 constexpr int kMaxGridSlots = 1024;  // workgroups of a persistent launch (slots per parity)
+// Slot memory of the grid reductions: region 0 = [2][kMaxGridSlots] for the
+// residual / barrier; region 1 = [2][3][kMaxGridSlots] for the three dot
+// products of the Barzilai-Borwein step size.
+constexpr int kBBSlotOffset = 2 * kMaxGridSlots;
+constexpr int kSlotWords = 8 * kMaxGridSlots;
 
 VFPI_DEV uint64_t ballot(bool p) { return __ballot(p); }
 

@@ -18,7 +18,7 @@ __global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t*
   const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i < n_nodes; i += stride) cmap[i] = -1;
-  for (int64_t i = i0; i < 2 * kMaxGridSlots; i += stride) slots[i] = 0ull;
+  for (int64_t i = i0; i < kSlotWords; i += stride) slots[i] = 0ull;
   if (i0 == 0) {
     flags[0] = 0;
     for (int k = 0; k < kSyncWords; ++k) sync[k] = 0u;
@@ -71,6 +71,12 @@ struct GridArgs {
   double* vprev;       // Chebyshev v^{l-1} buffer (streaming kernels)
   int32_t cheby_ls;    // 0: off
   double cheby_u;
+  // Barzilai-Borwein step sizes (k_vfpi_bb only)
+  int32_t bb2;                        // 0: BB1 s's/s'z, 1: BB2 s'z/z'z
+  double omega;                       // gamma_m = alpha + omega (S-contacts)
+  double* avbuf;                      // [n] A v^l of the previous sweep (own DOFs)
+  const unsigned long long* amax;     // max_d sum_j |a_dj| from the setup
+  double* tape_w;                     // nullable: receives the final alpha
 };
 
 // Persistent V-FPI kernel: the whole sweep loop of one step.  TPN = threads
@@ -163,6 +169,142 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
   }
 }
 
+
+// Persistent V-FPI kernel with Barzilai-Borwein step sizes W = alpha^l I
+// (Sec. IV-C.2): alpha^1 = 1 / max_d sum_j |a_dj| (Gershgorin), and for l >= 2
+// alpha^l = s's / s'z (BB1) or s'z / z'z (BB2) with s = v^l - v^{l-1},
+// z = A v^l - A v^{l-1}; the previous alpha is kept when the quotient is not
+// defined and positive.  A sweep has two phases: A v^l for the workgroup's own
+// rows (kept in avbuf for the next z) with the three dot products, one grid
+// reduction, then the rest of the sweep with gamma_m = alpha + omega and the
+// residual reduction of Alg. 1.  Thread = node, NW chunk slots per workgroup.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
+  constexpr bool COH = true;
+  constexpr int U = (64 * NW >= 960) ? 2 : 4;
+  __shared__ double s_red[NW];
+  __shared__ int s_ired[3 * NW];
+  const int G = gridDim.x;
+  const int lb = xcd_logical_block(blockIdx.x, G);
+  const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nch = (a.n_nodes + 63) / 64;
+  const int64_t c0 = lb * nch / G, c1 = (lb + 1) * nch / G;
+  const int passes = (int)((c1 - c0 + NW - 1) / NW);
+
+  const int flags = *a.flags;
+  if (flags != 0 || a.max_iters <= 0) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_contacts;
+         k += (int64_t)G * blockDim.x)
+      a.d.lambda[k] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.stats->iters = 0;
+      a.stats->status = flags ? flags : VFPI_S_MAXITER;
+      a.stats->theta = INFINITY;
+    }
+    return;
+  }
+  const SweepData<double>& d = a.d;
+  double* vcur = a.v_user;
+  double* vnext = a.v_alt;
+  double alpha = 1.0 / __builtin_bit_cast(double, (uint64_t)*a.amax);
+  int cb[3] = {0, 0, 0};
+  for (int l = 1;; ++l) {
+    // phase 1: A v^l of the own rows, s = v^l - v^{l-1}, z = A v^l - A v^{l-1}
+    double dots[3] = {0.0, 0.0, 0.0};  // s's, s'z, z'z
+    for (int p = 0; p < passes; ++p) {
+      const int64_t c = c0 + (int64_t)p * NW + slot;
+      const int64_t n0 = c * 64;
+      const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+      const int64_t i = n0 + lane;
+      const bool act = lane < cnt;
+      const int nk = act ? d.row_ptr[i + 1] - d.row_ptr[i] : 0;
+      const int64_t base = cnt > 0 ? d.row_ptr[n0] : 0;
+      double Av[3];
+      spmv_rows3<double, COH, U>(d.scol, d.sval, vcur, base, nk, lane, Av);
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const int64_t k = 3 * i + r;
+          if (l >= 2) {
+            const double s = ldv<COH>(vcur + k) - ldv<COH>(vnext + k);
+            const double z = Av[r] - a.avbuf[k];
+            dots[0] += s * s;
+            dots[1] += s * z;
+            dots[2] += z * z;
+          }
+          a.avbuf[k] = Av[r];
+        }
+      }
+    }
+    if (l >= 2) {
+      grid_sum3(a.slots + kBBSlotOffset, G, lb, l - 1, dots, s_red);
+      if (!a.bb2 && dots[0] > 0.0 && dots[1] > 0.0) alpha = dots[0] / dots[1];
+      else if (a.bb2 && dots[1] > 0.0 && dots[2] > 0.0) alpha = dots[1] / dots[2];
+    }
+    // phase 2: v* = v^l - alpha (A v^l - b), contact step, v^{l+1}
+    const double g = alpha + a.omega;
+    double th2 = 0.0;
+    cb[0] = cb[1] = cb[2] = 0;
+    for (int p = 0; p < passes; ++p) {
+      const int64_t c = c0 + (int64_t)p * NW + slot;
+      const int64_t n0 = c * 64;
+      const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+      const int64_t i = n0 + lane;
+      if (lane >= cnt) continue;
+      double v[3], vs[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        v[r] = ldv<COH>(vcur + 3 * i + r);
+        vs[r] = v[r] - alpha * (a.avbuf[3 * i + r] - d.b[3 * i + r]);
+      }
+      double vn[3] = {vs[0], vs[1], vs[2]};
+      const int m = d.cmap[i];
+      if (m >= 0) {
+        ContactRec<double> cr = load_contact<double>(d.cpack + kPack * (int64_t)m);
+        cr.g = g;
+        double lam[3], ls[3];
+        const int br = contact_solve<double>(cr, vs[0], vs[1], vs[2], d.proj, lam, ls);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
+          vn[r] = vs[r] + alpha * F;
+          d.lambda[3 * (int64_t)m + r] = lam[r];
+          if (d.tape_lamstar) d.tape_lamstar[3 * (int64_t)m + r] = ls[r];
+        }
+        if (d.tape_branch) d.tape_branch[m] = br;
+        cb[br] += 1;
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        stv<COH>(vnext + 3 * i + r, vn[r]);
+        const double dd = vn[r] - v[r];
+        th2 += dd * dd;
+      }
+    }
+    th2 = block_sum(th2, s_red);
+    const bool stop = grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+    double* t = vcur;
+    vcur = vnext;
+    vnext = t;
+    if (stop) break;
+  }
+  block_sum4_int(cb[0], cb[1], cb[2], s_ired);
+  add_counts(a.stats, cb[0], cb[1], cb[2]);
+  for (int p = 0; p < passes; ++p) {
+    const int64_t c = c0 + (int64_t)p * NW + slot;
+    const int64_t n0 = c * 64;
+    const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+    if (lane >= cnt) continue;
+    const int64_t i = n0 + lane;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double x = ldv<COH>(vcur + 3 * i + r);
+      if (vcur != a.v_user) a.v_user[3 * i + r] = x;
+      if (a.tape_v) a.tape_v[3 * i + r] = x;
+      if (a.tape_w) a.tape_w[3 * i + r] = alpha;
+    }
+  }
+}
 
 // Register-resident variant of the persistent kernel (variant kind 5): each
 // workgroup owns at most NW chunks (one pass), so a lane keeps, for the whole
@@ -362,16 +504,14 @@ Variant decode_variant(int32_t v, int32_t n_nodes) {
 // Cooperative launch of at most one workgroup per CU (capped by the number of
 // chunk groups and the caller's cap); the grid is a multiple of 8 above 8 so
 // the XCD-aware numbering is exact.
-template <int TPN, int NW>
-hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool single, hipStream_t st) {
-  auto kern = k_vfpi_grid<TPN, NW>;
-  const int threads = 64 * TPN * NW;
+hipError_t launch_persistent(void (*kern)(GridArgs), int threads, int nw, const GridArgs& ga, int grid_req,
+                             int num_cu, int n_nodes, bool single, hipStream_t st) {
   if (single) {
     hipLaunchKernelGGL(kern, dim3(1), dim3(threads), 0, st, ga);
     return hipGetLastError();
   }
   const int64_t nch = (n_nodes + 63) / 64;
-  int64_t g = (nch + NW - 1) / NW;
+  int64_t g = (nch + nw - 1) / nw;
   int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
   if (g > cap) g = cap;
   if (grid_req > 0 && grid_req < g) g = grid_req;
@@ -380,6 +520,16 @@ hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
   GridArgs arg = ga;
   void* params[] = {&arg};
   return hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, st);
+}
+
+template <int TPN, int NW>
+hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool single, hipStream_t st) {
+  return launch_persistent(k_vfpi_grid<TPN, NW>, 64 * TPN * NW, NW, ga, grid_req, num_cu, n_nodes, single, st);
+}
+
+template <int NW>
+hipError_t launch_bb(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool single, hipStream_t st) {
+  return launch_persistent(k_vfpi_bb<NW>, 64 * NW, NW, ga, grid_req, num_cu, n_nodes, single, st);
 }
 
 // Register-resident kernel: one pass per workgroup, so the grid must cover
@@ -402,6 +552,22 @@ hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
   }
   return hipLaunchCooperativeKernel((const void*)k_vfpi_regs<NW, KC, true>, dim3((unsigned)g), dim3(64 * NW), params,
                                     0, st);
+}
+
+// Barzilai-Borwein step sizes: the two-phase kernel, grid (kind 1) or one
+// workgroup (kind 3); the other kinds do not implement it.
+hipError_t launch_variant_bb(const Variant& vr, const GridArgs& ga, int num_cu, int N, hipStream_t stream) {
+  switch (vr.kind) {
+    case 1:
+      return (vr.nw <= 1)   ? launch_bb<1>(ga, vr.grid, num_cu, N, false, stream)
+             : (vr.nw <= 2) ? launch_bb<2>(ga, vr.grid, num_cu, N, false, stream)
+                            : launch_bb<4>(ga, vr.grid, num_cu, N, false, stream);
+    case 3:
+      return (vr.nw <= 4) ? launch_bb<4>(ga, 1, num_cu, N, true, stream)
+                          : launch_bb<16>(ga, 1, num_cu, N, true, stream);
+    default:
+      return hipErrorNotSupported;
+  }
 }
 
 hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int N, hipStream_t stream) {
@@ -440,7 +606,8 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
   int rc = vfpi_check_opts(opts, false);
   if (rc) return rc;
-  if (opts->w_mode == VFPI_W_BB1 || opts->w_mode == VFPI_W_BB2) return VFPI_E_UNSUPPORTED;
+  const bool bb = opts->w_mode == VFPI_W_BB1 || opts->w_mode == VFPI_W_BB2;
+  if (bb && opts->cheby_ls > 0) return VFPI_E_UNSUPPORTED;
   if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;  // a row with two blocks: D-contacts
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
   if (N == 0) {
@@ -466,8 +633,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ra.nnzb = A->nnzb;
   ra.w_mode = opts->w_mode;
   ra.reuse = opts->reuse_w != 0;
-  ra.alpha = opts->alpha_user;
+  ra.alpha = bb ? 1.0 : opts->alpha_user;  // BB: alpha is set on the device
   ra.omega = opts->omega;
+  ra.amax = bb ? reinterpret_cast<unsigned long long*>(ctx->sync + SY_AMAX) : nullptr;
   const int64_t nch = (N + 63) / 64;
   hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, stream, N, A->row_ptr, A->col_idx,
                      static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), ctx->diag,
@@ -502,12 +670,18 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.vprev = static_cast<double*>(ctx->vprev);
   ga.cheby_ls = opts->cheby_ls;
   ga.cheby_u = opts->cheby_u == 0.0 ? 1.0 : opts->cheby_u;
+  ga.bb2 = opts->w_mode == VFPI_W_BB2;
+  ga.omega = opts->omega;
+  ga.avbuf = ctx->adj;
+  ga.amax = reinterpret_cast<const unsigned long long*>(ctx->sync + SY_AMAX);
+  ga.tape_w = tv.w;
 
   Variant vr = decode_variant(opts->variant, N);
   if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
   vfpi_mark(ctx, 1, stream);
-  hipError_t e = launch_variant(vr, ga, ctx->num_cu, N, stream);
+  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream) : launch_variant(vr, ga, ctx->num_cu, N, stream);
   if (e == hipErrorInvalidValue) return VFPI_E_OPTS;
+  if (e == hipErrorNotSupported) return VFPI_E_UNSUPPORTED;
   vfpi_mark(ctx, 2, stream);
   return e == hipSuccess ? VFPI_OK : VFPI_E_HIP;
 }

@@ -63,6 +63,39 @@ VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, doub
   return block_sum(acc, s_red);
 }
 
+// Three partials at once (valid in every thread of the workgroup), in the slot
+// region `reg` = [2][3][kMaxGridSlots] with its own sequence numbers; the
+// same tagging and double-buffering argument as grid_sum applies per region.
+// Returns the fixed-order sums in x, in every thread.
+VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], double* s_red) {
+  if (G == 1) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) x[q] = block_sum(x[q], s_red);
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) x[q] = block_sum(x[q], s_red);
+  const unsigned tag = sync_tag(seq);
+  uint64_t* sl = reg + (seq & 1) * 3 * (int64_t)kMaxGridSlots;
+  drain();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) st_relaxed(sl + q * kMaxGridSlots + lb, tagged(x[q], tag));
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < G; k += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      uint64_t b;
+      while (((b = ld_relaxed(sl + q * kMaxGridSlots + k)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
+      acc[q] += untag(b);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) x[q] = block_sum(acc[q], s_red);
+}
+
 // Residual reduction + convergence test of Alg. 1 (theta < tol or l = l_max).
 // Every thread of every workgroup calls with the same seq.  `th2` is this
 // workgroup's partial (valid in thread 0).  Workgroup 0 writes iters,

@@ -17,7 +17,7 @@ namespace vfpi {
 constexpr int kSyncWords = 64;
 
 // Words of ctx->sync
-enum { SY_QUEUE = 2 };
+enum { SY_QUEUE = 2, SY_AMAX = 4 /* 64-bit, words 4-5 */ };
 
 }  // namespace vfpi
 
@@ -35,7 +35,7 @@ struct vfpi_ctx {
   int32_t* cmap = nullptr;     // [max_nodes] node -> contact (-1: none)
   void* cpack = nullptr;       // [12 max_contacts] R, phi, mu, gamma per contact
   double* adj = nullptr;       // [7 * 3 max_nodes] adjoint vectors
-  uint64_t* slots = nullptr;   // [2 * kMaxGridSlots] tagged per-workgroup partial sums
+  uint64_t* slots = nullptr;   // [kSlotWords] tagged per-workgroup partial sums
   uint32_t* sync = nullptr;    // [kSyncWords] work-queue counter of the batched kernel
   int32_t* flags = nullptr;    // [1 + max_envs] device-detected data errors
   int32_t stats_nodes = -1;    // N for which diag/rn2 hold valid row sums (W reuse)

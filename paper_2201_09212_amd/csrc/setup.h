@@ -61,6 +61,7 @@ struct RowsArgs {
   bool reuse;
   double alpha;
   double omega;  // invertible contact: the contact step divides by gamma + omega
+  unsigned long long* amax = nullptr;  // nullable: max_d sum_j |a_dj| (bits of a non-negative double)
 };
 
 // One wave converts one chunk of <= 64 consecutive nodes [n0, n0 + cnt).
@@ -92,7 +93,7 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
     return;
   }
   const int64_t base = row_ptr[n0];
-  double d[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+  double d[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0}, ab[3] = {0.0, 0.0, 0.0};
   bool has_diag = false, fin = true, badcol = false;
   int64_t off = 0;
   for (int k = 0;; ++k) {
@@ -118,7 +119,10 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
       }
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) s[r] += (double)x[3 * r + cc] * (double)x[3 * r + cc];
+        for (int cc = 0; cc < 3; ++cc) {
+          s[r] += (double)x[3 * r + cc] * (double)x[3 * r + cc];
+          ab[r] += fabs((double)x[3 * r + cc]);
+        }
       if (c == i) {
         has_diag = true;
         d[0] = x[0];
@@ -135,6 +139,10 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
     if (vvec) fin &= finite(vvec[3 * i + r]);
   }
   if (badcol) set_flag(flag, VFPI_S_BAD_PATTERN);
+  if (ra.amax) {  // Gershgorin bound for the first Barzilai-Borwein step (order-free max)
+    const double mx = fmax(ab[0], fmax(ab[1], ab[2]));
+    if (mx >= 0.0) atomicMax(ra.amax, (unsigned long long)__builtin_bit_cast(uint64_t, mx));
+  }
   if (!fin) set_flag(flag, VFPI_S_NONFINITE);
   if (ra.reuse) {
 #pragma unroll

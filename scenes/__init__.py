@@ -13,7 +13,7 @@ from .problem import Problem, concat_problems, rng
 from .geometry import onb_duff, contacts_from_gaps
 from .cloth import ClothScene, cloth_cfg1, cloth_cfg2, cloth_cfg4_envs, cloth_cfg5_scene
 from .fem import FemScene, fem_cfg3, fem_ctx
-from .random import random_problem, inclined_plane_particles
+from .random import random_problem, inclined_plane_particles, two_level_diagonal
 
 __all__ = [
     "Problem", "concat_problems", "rng", "onb_duff", "contacts_from_gaps",

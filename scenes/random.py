@@ -70,3 +70,24 @@ def inclined_plane_particles(alpha, mu, mass=1.0, h=0.01, g=9.81, v_k=None, phi=
                    c_node=np.arange(n_p), c_node_j=np.full(n_p, -1),
                    R=R, phi=np.zeros(n_p) if phi is None else phi, mu=mu,
                    meta={"scene": "inclined_plane", "h": h, "g": g})
+
+
+def two_level_diagonal(n_nodes: int, seed: int, *, low=1.0, high=4.0, in_low_space=True) -> tuple:
+    """Contact-free problem with A = diag(low on the first half of the nodes,
+    high on the rest) and a warm start whose error x* - v0 lies in the `low`
+    eigenspace only (or in both with ``in_low_space=False``).  Returns
+    (problem, x*) with x* = A^-1 b.  Gershgorin gives alpha^1 = 1/high."""
+    g = rng("two_level", seed, "vectors")
+    half = n_nodes // 2
+    dvec = np.where(np.arange(3 * n_nodes) < 3 * half, low, high)
+    val = np.zeros((n_nodes, 3, 3))
+    for k in range(3):
+        val[:, k, k] = dvec[k::3]
+    x = g.normal(size=3 * n_nodes)
+    e = g.normal(size=3 * n_nodes)
+    if in_low_space:
+        e[3 * half:] = 0.0
+    p = Problem(n_nodes, np.arange(n_nodes + 1), np.arange(n_nodes), val, dvec * x, x - e,
+                np.zeros(0), np.zeros(0), np.zeros((0, 3, 3)), np.zeros(0), np.zeros(0),
+                meta={"name": f"two_level{n_nodes}"})
+    return p, x

@@ -1,0 +1,74 @@
+"""Barzilai-Borwein step sizes (Sec. IV-C.2) on the GPU vs the FP64 oracle:
+1e-9 at fixed sweep counts up to 30 (beyond that the quotients are formed from
+differences near the rounding floor, where any two summation orders part), the
+one-eigenspace closed form, and the converged solution against Frobenius W."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2201_09212_amd as vf
+import scenes
+from paper_2201_09212_amd import _abi
+from tests.gpu_util import gpu_step, rel, say, solver_for, upload
+
+pytestmark = pytest.mark.gpu
+
+# kind | chunk slots << 8 | workgroup cap << 16
+VARIANTS = {"grid_node1": 1 | (1 << 8), "grid_node2": 1 | (2 << 8), "grid_node4_cap8": 1 | (4 << 8) | (8 << 16),
+            "wg1_node4": 3 | (4 << 8), "wg1_node16": 3 | (16 << 8)}
+
+
+def _problems():
+    sc, x, v = scenes.cloth_cfg1(0)
+    yield "cloth10", sc.assemble(x, v), 12
+    yield "random700", scenes.random_problem(700, 300, 4, degree=5.0, phi_scale=0.5), 30
+    sc, x, v = scenes.cloth_cfg2(0)
+    yield "cloth128", sc.assemble(x, v), 30
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("mode", ["bb1", "bb2"])
+def test_bb_fixed_sweeps_parity(variant, mode):
+    for name, p, L in _problems():
+        if name == "cloth128" and variant.startswith("wg1"):
+            continue
+        ref = oracle.vfpi(p, max_iters=L, fixed_iters=True, w_mode=mode)
+        v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, w_mode=mode, variant=VARIANTS[variant])
+        ev, el = rel(v, ref["v"]), rel(lam, ref["lam"])
+        say(f"  {name} {variant} {mode} L={L}: rel_v={ev:.2e} rel_lam={el:.2e} alpha={ref['alpha']:.4e}")
+        assert st["iters"] == L and ev <= 1e-9 and el <= 1e-9
+
+
+@pytest.mark.parametrize("mode", ["bb1", "bb2"])
+def test_bb_one_eigenspace_closed_form(mode):
+    p, x = scenes.two_level_diagonal(300, 0)
+    for var in (VARIANTS["grid_node1"], VARIANTS["wg1_node4"]):
+        v, _, st, _ = gpu_step(p, max_iters=3, fixed_iters=True, w_mode=mode, variant=var)
+        say(f"  two_level300 {mode} variant {var:#x}: |v - x*| = {np.abs(v.ravel() - x).max():.2e}")
+        assert np.abs(v.ravel() - x).max() <= 1e-14 and st["theta"] <= 1e-14
+
+
+def test_bb_converged_matches_frobenius_and_omega():
+    p = scenes.random_problem(700, 300, 4, degree=5.0, phi_scale=0.5)
+    ref = gpu_step(p, max_iters=100000, tol=1e-12)
+    for mode in ("bb1", "bb2"):
+        v, lam, st, _ = gpu_step(p, max_iters=100000, tol=1e-12, w_mode=mode)
+        say(f"  random700 {mode}: {st['iters']} sweeps (Frobenius {ref[2]['iters']}), "
+            f"rel_v={rel(v, ref[0]):.2e}")
+        assert st["status"] == _abi.VFPI_S_CONVERGED
+        assert rel(v, ref[0]) <= 1e-9 and rel(lam, ref[1]) <= 1e-8
+    L = 25
+    o = oracle.vfpi(p, max_iters=L, fixed_iters=True, w_mode="bb1", omega=0.05)
+    v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, w_mode="bb1", omega=0.05)
+    assert rel(v, o["v"]) <= 1e-9 and rel(lam, o["lam"]) <= 1e-9
+
+
+def test_bb_unsupported_combinations():
+    p = scenes.random_problem(100, 20, 1)
+    s = solver_for(p)
+    A, Jc, b, v = upload(p)
+    with pytest.raises(vf.VfpiError, match="not supported"):
+        s.step(A, b, Jc, v, w_mode="bb1", cheby_ls=5)
+    for kind in (2, 4, 5):
+        with pytest.raises(vf.VfpiError, match="not supported"):
+            s.step(A, b, Jc, v.clone(), w_mode="bb2", variant=kind)

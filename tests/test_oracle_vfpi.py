@@ -222,3 +222,26 @@ def test_invertible_contact_recovers_impulse_from_velocity(omega):
     # and it differs from the exact (omega = 0) model
     r0 = oracle.vfpi(p, max_iters=200000, tol=1e-15)
     assert np.abs(r0["v"] - r["v"]).max() > 1e-6 * omega
+
+
+@pytest.mark.parametrize("mode", ["bb1", "bb2"])
+def test_bb_step_is_exact_on_one_eigenspace(mode):
+    """A = diag(1, 4) (Gershgorin alpha^1 = 1/4), error in the eigenvalue-1 space:
+    sweep 1 shrinks it by 3/4, so s and z = A s lie in that space and both BB
+    quotients give alpha^2 = 1 exactly; sweep 2 then lands on A^-1 b and sweep 3
+    does not move (Sec. IV-C.2)."""
+    p, x = scenes.two_level_diagonal(20, 0)
+    r1 = oracle.vfpi(p, max_iters=1, fixed_iters=True, w_mode=mode)
+    np.testing.assert_allclose(r1["v"] - x, 0.75 * (p.v0 - x), atol=1e-15)
+    r = oracle.vfpi(p, max_iters=3, fixed_iters=True, w_mode=mode, history=True)
+    assert r["alpha"] == 1.0
+    np.testing.assert_allclose(r["v"], x, atol=1e-14)
+    assert r["history"][2] <= 1e-14 and r["history"][1] > 0.1
+
+
+@pytest.mark.parametrize("mode", ["bb1", "bb2"])
+def test_bb_converges_on_two_eigenvalues(mode):
+    p, x = scenes.two_level_diagonal(20, 1, in_low_space=False)
+    r = oracle.vfpi(p, max_iters=200, tol=1e-13, w_mode=mode)
+    assert r["iters"] < 200
+    np.testing.assert_allclose(r["v"], x, atol=1e-12)
