@@ -91,3 +91,21 @@ def two_level_diagonal(n_nodes: int, seed: int, *, low=1.0, high=4.0, in_low_spa
                 np.zeros(0), np.zeros(0), np.zeros((0, 3, 3)), np.zeros(0), np.zeros(0),
                 meta={"name": f"two_level{n_nodes}"})
     return p, x
+
+
+def colliding_particle_pairs(m_i, m_j, normal, v_i, v_j, mu, h=0.01, g=9.81) -> Problem:
+    """K independent particle pairs (i = 2k, j = 2k + 1), each pair in one
+    D-contact whose frame R has ``normal`` (pointing from j to i) as its first
+    row: A = diag(m I), b = m (v_k + h g), phi = 0."""
+    m_i, m_j, mu = (np.atleast_1d(np.asarray(x, dtype=np.float64)) for x in (m_i, m_j, mu))
+    K = m_i.shape[0]
+    nrm = np.asarray(normal, dtype=np.float64).reshape(K, 3)
+    nrm = nrm / np.linalg.norm(nrm, axis=1, keepdims=True)
+    mass = np.stack([m_i, m_j], 1).reshape(-1)
+    val = mass[:, None, None] * np.eye(3)
+    vk = np.stack([np.asarray(v_i).reshape(K, 3), np.asarray(v_j).reshape(K, 3)], 1).reshape(-1, 3)
+    b = (mass[:, None] * (vk + h * np.array([0.0, 0.0, -g]))).reshape(-1)
+    n = 2 * K
+    return Problem(n_nodes=n, row_ptr=np.arange(n + 1), col_idx=np.arange(n), val=val, b=b, v0=vk.reshape(-1),
+                   c_node=2 * np.arange(K), c_node_j=2 * np.arange(K) + 1, R=onb_duff(nrm), phi=np.zeros(K),
+                   mu=mu, meta={"scene": "particle_pairs"})
