@@ -27,6 +27,8 @@ struct AdjArgs {
   int32_t n_nodes, n_contacts, nnzb;
   const int32_t* row_ptr;
   const int32_t* col_idx;
+  const double* val;       // A in the caller's layout (rows of D-contact partners)
+  const int32_t* cpair;    // contact nodes i, j (j = -1: S); nullptr: S only
   const int32_t* scol;
   const double* sval;
   const double* w;
@@ -93,6 +95,38 @@ VFPI_DEV void gt_node(const AdjArgs& a, int64_t i, int m, const double u[3], dou
   for (int r = 0; r < 3; ++r) out[r] -= R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
 }
 
+// D-contact m (J_m = [R, -R] on nodes i, j) seen from one of its nodes:
+// (G^T u) there = u_x -+ R^T D_P^T R (w_i u_i - w_j u_j) / g.
+VFPI_DEV void gt_pair(const AdjArgs& a, int m, bool first, const double ui[3], const double uj[3], double out[3]) {
+  const double* R = a.cpack + kPack * (int64_t)m;
+  const int64_t i = a.cpair[2 * (int64_t)m], j = a.cpair[2 * (int64_t)m + 1];
+  const double fi = a.w[3 * i] / R[11], fj = a.w[3 * j] / R[11];
+  double x[3], y[3], dmu;
+  for (int k = 0; k < 3; ++k)
+    x[k] = (R[3 * k] * ui[0] + R[3 * k + 1] * ui[1] + R[3 * k + 2] * ui[2]) * fi -
+           (R[3 * k] * uj[0] + R[3 * k + 1] * uj[1] + R[3 * k + 2] * uj[2]) * fj;
+  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+  const double* u = first ? ui : uj;
+  for (int r = 0; r < 3; ++r) {
+    const double f = R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
+    out[r] = first ? u[r] - f : u[r] + f;
+  }
+}
+
+VFPI_DEV bool adj_isd(const AdjArgs& a, int m) { return m >= 0 && a.cpair && a.cpair[2 * (int64_t)m + 1] >= 0; }
+
+// (A y)_x from A's block row x in the caller's layout; y read coherently.
+VFPI_DEV void arow_bsr(const AdjArgs& a, const double* y, int64_t x, double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  const int64_t r1 = a.row_ptr[x + 1];
+  for (int64_t k = a.row_ptr[x]; k < r1; ++k) {
+    const int64_t c = a.col_idx[k];
+    const double* B = a.val + 9 * k;
+    const double y0 = ldv<true>(y + 3 * c), y1 = ldv<true>(y + 3 * c + 1), y2 = ldv<true>(y + 3 * c + 2);
+    for (int r = 0; r < 3; ++r) out[r] += B[3 * r] * y0 + B[3 * r + 1] * y1 + B[3 * r + 2] * y2;
+  }
+}
+
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
   __shared__ double s_red[NW];
@@ -141,11 +175,11 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         const double* R = a.cpack + kPack * (int64_t)m;
         double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
         dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
-        const double gi = 1.0 / R[11];
+        const double gi = (adj_isd(a, m) && a.cpair[2 * (int64_t)m] != i) ? -1.0 / R[11] : 1.0 / R[11];
         for (int r = 0; r < 3; ++r) e[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
       }
       for (int r = 0; r < 3; ++r) {
-        a.E[3 * i + r] = e[r];
+        stv<true>(a.E + 3 * i + r, e[r]);
         stv<true>(a.S[1] + 3 * i + r, a.w[3 * i + r] * e[r]);
       }
     });
@@ -162,12 +196,27 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
     }
     if (!act) return;
     double u[3], t[3];
-    for (int r = 0; r < 3; ++r) u[r] = a.gl ? a.gv[3 * i + r] - a.E[3 * i + r] + Ap[r] : a.gv[3 * i + r];
-    gt_node(a, i, a.cmap[i], u, t);
+    const int m = a.cmap[i];
+    if (adj_isd(a, m)) {  // u0 of both nodes of the pair, from A's rows
+      double uu[2][3];
+      for (int s = 0; s < 2; ++s) {
+        const int64_t z = a.cpair[2 * (int64_t)m + s];
+        double Az[3] = {0.0, 0.0, 0.0};
+        if (a.gl) arow_bsr(a, a.S[1], z, Az);
+        for (int r = 0; r < 3; ++r)
+          uu[s][r] = a.gl ? a.gv[3 * z + r] - ldv<true>(a.E + 3 * z + r) + Az[r] : a.gv[3 * z + r];
+      }
+      const bool first = a.cpair[2 * (int64_t)m] == i;
+      gt_pair(a, m, first, uu[0], uu[1], t);
+      for (int r = 0; r < 3; ++r) u[r] = first ? uu[0][r] : uu[1][r];
+    } else {
+      for (int r = 0; r < 3; ++r) u[r] = a.gl ? a.gv[3 * i + r] - ldv<true>(a.E + 3 * i + r) + Ap[r] : a.gv[3 * i + r];
+      gt_node(a, i, m, u, t);
+    }
     for (int r = 0; r < 3; ++r) {
-      a.gt[3 * i + r] = u[r];
-      a.U[0][3 * i + r] = u[r];
-      a.T[0][3 * i + r] = t[r];
+      stv<true>(a.gt + 3 * i + r, u[r]);
+      stv<true>(a.U[0] + 3 * i + r, u[r]);
+      stv<true>(a.T[0] + 3 * i + r, t[r]);
       stv<true>(a.S[0] + 3 * i + r, a.w[3 * i + r] * t[r]);
     }
   });
@@ -187,13 +236,27 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         spmv_rows3<double, true>(a.scol, a.sval, a.S[cur], cnt > 0 ? a.row_ptr[n0] : 0, nk, lane, As);
         if (!act) return;
         double un[3], tn[3];
-        for (int r = 0; r < 3; ++r) un[r] = a.gt[3 * i + r] + a.T[cur][3 * i + r] - As[r];
-        gt_node(a, i, a.cmap[i], un, tn);
+        const int m = a.cmap[i];
+        if (adj_isd(a, m)) {  // u of both nodes of the pair, from A's rows
+          double uu[2][3];
+          for (int s = 0; s < 2; ++s) {
+            const int64_t z = a.cpair[2 * (int64_t)m + s];
+            double Az[3];
+            arow_bsr(a, a.S[cur], z, Az);
+            for (int r = 0; r < 3; ++r) uu[s][r] = ldv<true>(a.gt + 3 * z + r) + ldv<true>(a.T[cur] + 3 * z + r) - Az[r];
+          }
+          const bool first = a.cpair[2 * (int64_t)m] == i;
+          gt_pair(a, m, first, uu[0], uu[1], tn);
+          for (int r = 0; r < 3; ++r) un[r] = first ? uu[0][r] : uu[1][r];
+        } else {
+          for (int r = 0; r < 3; ++r) un[r] = ldv<true>(a.gt + 3 * i + r) + ldv<true>(a.T[cur] + 3 * i + r) - As[r];
+          gt_node(a, i, m, un, tn);
+        }
         for (int r = 0; r < 3; ++r) {
-          const double d = un[r] - a.U[cur][3 * i + r];
+          const double d = un[r] - ldv<true>(a.U[cur] + 3 * i + r);
           th2 += d * d;
-          a.U[nxt][3 * i + r] = un[r];
-          a.T[nxt][3 * i + r] = tn[r];
+          stv<true>(a.U[nxt] + 3 * i + r, un[r]);
+          stv<true>(a.T[nxt] + 3 * i + r, tn[r]);
           stv<true>(a.S[nxt] + 3 * i + r, a.w[3 * i + r] * tn[r]);
         }
       });
@@ -214,21 +277,37 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
     if (lane >= cnt) return;
     const int64_t i = n0 + lane;
     const int m = a.cmap[i];
-    double u[3] = {u_fin[3 * i], u_fin[3 * i + 1], u_fin[3 * i + 2]};
+    double u[3] = {ldv<true>(u_fin + 3 * i), ldv<true>(u_fin + 3 * i + 1), ldv<true>(u_fin + 3 * i + 2)};
     double q[3] = {u[0], u[1], u[2]};
     if (m >= 0) {
       const double* R = a.cpack + kPack * (int64_t)m;
-      const double wb = a.w[3 * i];
-      double rr[3], y[3], dmu;
+      const bool isd = adj_isd(a, m);
+      const bool first = !isd || a.cpair[2 * (int64_t)m] == i;
+      // r = J_m W u + g_lam (both nodes of a D-contact)
+      const int64_t ni = isd ? a.cpair[2 * (int64_t)m] : i;
+      double ui[3], rr[3], y[3], dmu;
+      for (int r = 0; r < 3; ++r) ui[r] = ldv<true>(u_fin + 3 * ni + r);
+      const double wi = a.w[3 * ni];
       for (int k = 0; k < 3; ++k) {
-        rr[k] = R[3 * k] * (wb * u[0]) + R[3 * k + 1] * (wb * u[1]) + R[3 * k + 2] * (wb * u[2]);
+        rr[k] = R[3 * k] * (wi * ui[0]) + R[3 * k + 1] * (wi * ui[1]) + R[3 * k + 2] * (wi * ui[2]);
         if (a.gl) rr[k] += a.gl[3 * (int64_t)m + k];
+      }
+      if (isd) {
+        const int64_t nj = a.cpair[2 * (int64_t)m + 1];
+        double uj[3];
+        for (int r = 0; r < 3; ++r) uj[r] = ldv<true>(u_fin + 3 * nj + r);
+        const double wj = a.w[3 * nj];
+        for (int k = 0; k < 3; ++k)
+          rr[k] -= R[3 * k] * (wj * uj[0]) + R[3 * k + 1] * (wj * uj[1]) + R[3 * k + 2] * (wj * uj[2]);
       }
       dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], rr, y, &dmu);
       const double gi = 1.0 / R[11];
-      for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
-      a.grad_phi[m] = -y[0] * gi;
-      a.grad_mu[m] = dmu;
+      const double sg = first ? gi : -gi;
+      for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * sg;
+      if (first) {
+        a.grad_phi[m] = -y[0] * gi;
+        a.grad_mu[m] = dmu;
+      }
     }
     double bb[3];
     for (int r = 0; r < 3; ++r) {
@@ -269,7 +348,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
   if (opts->max_iters < 0 || !(opts->tol >= 0.0)) return VFPI_E_OPTS;
   if (opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
-  if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;
+  if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
   if (N == 0) {
     hipLaunchKernelGGL(k_stats_empty, dim3(1), dim3(1), 0, stream, stats);
     VFPI_CHECK_HIP(hipGetLastError());
@@ -286,7 +365,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
-                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->flags, 1e-10);
+                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->cpair, ctx->flags, 1e-10);
   // W comes from the forward tape; the row pass rebuilds the interleaved copy of A.
   RowsArgs ra;
   ra.nnzb = A->nnzb;
@@ -299,6 +378,9 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
                      static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), nullptr, nullptr,
                      ra, tv.w, ctx->cmap, cpack, w, nullptr, grad_v, tv.v,
                      ctx->flags);
+  if (nc > 0 && Jc->nnzb > nc)
+    hipLaunchKernelGGL(k_pairs<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, ctx->cpair, nullptr,
+                       nullptr, ra, w, nullptr, cpack, ctx->flags);
   VFPI_CHECK_HIP(hipGetLastError());
 
   const int64_t n = 3 * (int64_t)N;
@@ -308,6 +390,8 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   aa.nnzb = A->nnzb;
   aa.row_ptr = A->row_ptr;
   aa.col_idx = A->col_idx;
+  aa.val = static_cast<const double*>(A->val);
+  aa.cpair = (Jc->nnzb > nc) ? ctx->cpair : nullptr;
   aa.scol = ctx->scol;
   aa.sval = static_cast<const double*>(ctx->sval);
   aa.w = w;

@@ -16,7 +16,7 @@ hipError_t alloc(T** p, size_t count) {
 
 void release(vfpi_ctx* c) {
   void* ptrs[] = {c->scol, c->sval, c->diag, c->rn2, c->w, c->vbuf, c->vprev, c->cmap, c->cpack,
-                  c->adj, c->slots, c->sync, c->flags};
+                  c->cpair, c->adj, c->slots, c->sync, c->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 3; ++k)
@@ -60,6 +60,7 @@ extern "C" int vfpi_create(vfpi_ctx** out, int32_t max_nodes, int32_t max_nnzb, 
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->vprev), n);
   if (e == hipSuccess) e = alloc(&c->cmap, (size_t)max_nodes);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->cpack), vfpi::kPack * (size_t)max_contacts);
+  if (e == hipSuccess) e = alloc(&c->cpair, 2 * (size_t)max_contacts);
   if (e == hipSuccess) e = alloc(&c->adj, 8 * n);
   if (e == hipSuccess) e = alloc(&c->slots, (size_t)vfpi::kSlotWords);
   if (e == hipSuccess) e = alloc(&c->sync, (size_t)vfpi::kSyncWords);

@@ -38,6 +38,8 @@ struct BatchArgs {
   float* w;
   int32_t* cmap;
   float* cpack;
+  int32_t* cpair;      // contact nodes (D-contacts)
+  int32_t has_d;       // some J_c row has two blocks
   float* v_user;
   float* v_alt;
   float* lambda;
@@ -98,8 +100,8 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
     for (int64_t i = n_lo + threadIdx.x; i < n_hi; i += blockDim.x) a.cmap[i] = -1;
     __syncthreads();
     for (int64_t m = m_lo + threadIdx.x; m < m_hi; m += blockDim.x)
-      contact_setup<float>(m, a.nnzb_c, a.crp, a.ccol, a.cval, a.phi, a.mu, n_lo, n_hi, a.cmap, a.cpack, &s_flag,
-                           1e-5);
+      contact_setup<float>(m, a.nnzb_c, a.crp, a.ccol, a.cval, a.phi, a.mu, n_lo, n_hi, a.cmap, a.cpack, a.cpair,
+                           &s_flag, 1e-5);
     __syncthreads();
     const int64_t nn = n_hi - n_lo;
     const int64_t nch = (nn + 63) / 64;
@@ -110,6 +112,11 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
                         &s_flag);
     }
     __syncthreads();
+    if (a.has_d) {
+      for (int64_t m = m_lo + threadIdx.x; m < m_hi; m += blockDim.x)
+        pair_setup<float>(m, a.cpair, a.diag, a.rn2, a.ra, a.w, nullptr, a.cpack, &s_flag);
+      __syncthreads();
+    }
     const int flag = s_flag;
     if (flag != 0 || a.max_iters <= 0) {
       for (int64_t k = 3 * m_lo + threadIdx.x; k < 3 * m_hi; k += blockDim.x) a.lambda[k] = 0.0f;
@@ -136,6 +143,9 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
     d.tape_lamstar = nullptr;
     d.tape_branch = nullptr;
     d.proj = a.proj;
+    d.col_idx = a.col_idx;
+    d.val = a.val;
+    d.cpair = a.has_d ? a.cpair : nullptr;
     Cheby ch;
     ch.ls = a.cheby_ls;
     ch.u = a.cheby_u;
@@ -231,7 +241,7 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
     return VFPI_E_CAPACITY;
   int rc = vfpi_check_opts(opts, true);
   if (rc) return rc;
-  if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;
+  if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
   if (n_env == 0) return VFPI_OK;
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -261,6 +271,8 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   ba.w = static_cast<float*>(ctx->w);
   ba.cmap = ctx->cmap;
   ba.cpack = static_cast<float*>(ctx->cpack);
+  ba.cpair = ctx->cpair;
+  ba.has_d = Jc->nnzb > nc;
   ba.v_user = v;
   ba.v_alt = static_cast<float*>(ctx->vbuf);
   ba.lambda = lambda;

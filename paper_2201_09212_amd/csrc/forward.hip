@@ -38,10 +38,19 @@ __global__ void k_stats_empty(vfpi_stats* st) {
 
 template <class T>
 __global__ void k_contacts(int32_t nc, int32_t nnzb_c, const int32_t* crp, const int32_t* ccol, const T* cval,
-                           const T* phi, const T* mu, int32_t n_nodes, int32_t* cmap, T* cpack, int32_t* flags,
-                           double orth_tol) {
+                           const T* phi, const T* mu, int32_t n_nodes, int32_t* cmap, T* cpack, int32_t* cpair,
+                           int32_t* flags, double orth_tol) {
   int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (m < nc) contact_setup<T>(m, nnzb_c, crp, ccol, cval, phi, mu, 0, n_nodes, cmap, cpack, flags, orth_tol);
+  if (m < nc)
+    contact_setup<T>(m, nnzb_c, crp, ccol, cval, phi, mu, 0, n_nodes, cmap, cpack, cpair, flags, orth_tol);
+}
+
+// Shared W and gamma of every D-contact pair (after the row pass).
+template <class T>
+__global__ void k_pairs(int32_t nc, const int32_t* cpair, const double* diag, const double* rn2, RowsArgs ra, T* w,
+                        double* tape_w, T* cpack, int32_t* flags) {
+  int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (m < nc) pair_setup<T>(m, cpair, diag, rn2, ra, w, tape_w, cpack, flags);
 }
 
 template <class T>
@@ -259,7 +268,19 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
       }
       double vn[3] = {vs[0], vs[1], vs[2]};
       const int m = d.cmap[i];
-      if (m >= 0) {
+      if (m >= 0 && is_dcontact(d, m)) {  // gamma = w_i + w_j = 2 alpha (+ omega)
+        double lam[3], ls[3];
+        int br;
+        if (dcontact_node<double, COH>(d, vcur, nullptr, alpha, 2.0 * alpha + a.omega, i, m, vs, vn, lam, ls, br)) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            d.lambda[3 * (int64_t)m + r] = lam[r];
+            if (d.tape_lamstar) d.tape_lamstar[3 * (int64_t)m + r] = ls[r];
+          }
+          if (d.tape_branch) d.tape_branch[m] = br;
+          cb[br] += 1;
+        }
+      } else if (m >= 0) {
         ContactRec<double> cr = load_contact<double>(d.cpack + kPack * (int64_t)m);
         cr.g = g;
         double lam[3], ls[3];
@@ -377,6 +398,8 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     m = d.cmap[i];
     if (m >= 0) cr = load_contact<double>(d.cpack + kPack * (int64_t)m);
   }
+  const bool isd = m >= 0 && is_dcontact(d, m);
+  const bool owner = !isd || d.cpair[2 * (int64_t)m] == i;  // reports lambda
   double lam[3] = {0.0, 0.0, 0.0}, ls[3] = {0.0, 0.0, 0.0};
   double vp[3] = {vo[0], vo[1], vo[2]};  // v^{l-1} for Chebyshev acceleration (v^0 = v^1)
   int br = BR_OPEN;
@@ -416,7 +439,9 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         vs[r] = vo[r] - wi[r] * (Av[r] - bi[r]);
         vn[r] = vs[r];
       }
-      if (m >= 0) {
+      if (isd) {
+        (void)dcontact_node<double, COH>(d, vcur, d.w, 0.0, 0.0, i, m, vs, vn, lam, ls, br);
+      } else if (m >= 0) {
         br = contact_solve<double>(cr, vs[0], vs[1], vs[2], d.proj, lam, ls);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -459,7 +484,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     ch.observe(theta);
   }
   int cb[3] = {0, 0, 0};
-  if (act && m >= 0) {
+  if (act && m >= 0 && owner) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       d.lambda[3 * (int64_t)m + r] = lam[r];
@@ -608,7 +633,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   if (rc) return rc;
   const bool bb = opts->w_mode == VFPI_W_BB1 || opts->w_mode == VFPI_W_BB2;
   if (bb && opts->cheby_ls > 0) return VFPI_E_UNSUPPORTED;
-  if (Jc->nnzb > nc) return VFPI_E_UNSUPPORTED;  // a row with two blocks: D-contacts
+  if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;  // at most two blocks per contact row
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
   if (N == 0) {
     hipLaunchKernelGGL(k_stats_empty, dim3(1), dim3(1), 0, stream, stats);
@@ -628,7 +653,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
-                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->flags, 1e-10);
+                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->cpair, ctx->flags, 1e-10);
   RowsArgs ra;
   ra.nnzb = A->nnzb;
   ra.w_mode = opts->w_mode;
@@ -641,6 +666,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
                      static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), ctx->diag,
                      ctx->rn2, ra, static_cast<const double*>(opts->w_user), ctx->cmap, cpack, w, tv.w, b, v,
                      ctx->flags);
+  if (nc > 0 && Jc->nnzb > nc)
+    hipLaunchKernelGGL(k_pairs<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, ctx->cpair, ctx->diag,
+                       ctx->rn2, ra, w, tv.w, cpack, ctx->flags);
   VFPI_CHECK_HIP(hipGetLastError());
   ctx->stats_nodes = N;
 
@@ -656,6 +684,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.d.tape_lamstar = tv.lamstar;
   ga.d.tape_branch = tv.branch;
   ga.d.proj = opts->projection;
+  ga.d.col_idx = A->col_idx;
+  ga.d.val = static_cast<const double*>(A->val);
+  ga.d.cpair = (Jc->nnzb > nc) ? ctx->cpair : nullptr;
   ga.n_nodes = N;
   ga.n_contacts = nc;
   ga.v_user = v;

@@ -34,7 +34,8 @@ struct vfpi_ctx {
   void* vprev = nullptr;       // [3 max_nodes] v^{l-1} for Chebyshev acceleration (node-local)
   int32_t* cmap = nullptr;     // [max_nodes] node -> contact (-1: none)
   void* cpack = nullptr;       // [12 max_contacts] R, phi, mu, gamma per contact
-  double* adj = nullptr;       // [7 * 3 max_nodes] adjoint vectors
+  int32_t* cpair = nullptr;    // [2 max_contacts] nodes i, j of each contact (j = -1: S)
+  double* adj = nullptr;       // [8 * 3 max_nodes] adjoint vectors (forward BB: A v^l)
   uint64_t* slots = nullptr;   // [kSlotWords] tagged per-workgroup partial sums
   uint32_t* sync = nullptr;    // [kSyncWords] work-queue counter of the batched kernel
   int32_t* flags = nullptr;    // [1 + max_envs] device-detected data errors

@@ -11,31 +11,55 @@
 
 namespace vfpi {
 
+// Contact m: one block row of J_c with either one block R at node i
+// (S-contact) or, when `cpair` is given, two blocks R at node i and -R at node
+// j != i (D-contact, eq. jcnode); anything else is NOT_NODAL.  Both nodes enter
+// the node -> contact map; cpair[2m], cpair[2m+1] = i, j (-1 for S).
 template <class T>
 VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict__ crp,
                             const int32_t* __restrict__ ccol, const T* __restrict__ cval,
                             const T* __restrict__ phi, const T* __restrict__ mu, int64_t node_lo,
-                            int64_t node_hi, int32_t* cmap, T* cpack, int32_t* flag, double orth_tol) {
-  int64_t r0 = crp[m], r1 = crp[m + 1];
-  if (r1 - r0 != 1 || r0 < 0 || r1 > nnzb_c) {
+                            int64_t node_hi, int32_t* cmap, T* cpack, int32_t* cpair, int32_t* flag,
+                            double orth_tol) {
+  if (cpair) {  // a rejected row must not leave a stale pair behind
+    cpair[2 * m] = -1;
+    cpair[2 * m + 1] = -1;
+  }
+  const int64_t r0 = crp[m], r1 = crp[m + 1];
+  const int64_t nb = r1 - r0;
+  if ((nb != 1 && !(nb == 2 && cpair)) || r0 < 0 || r1 > nnzb_c) {
     set_flag(flag, VFPI_S_NOT_NODAL);
     return;
   }
-  int64_t i = ccol[r0];
-  if (i < node_lo || i >= node_hi) {
+  const int64_t i = ccol[r0];
+  const int64_t j = nb == 2 ? ccol[r0 + 1] : -1;
+  if (i < node_lo || i >= node_hi || (nb == 2 && (j < node_lo || j >= node_hi))) {
     set_flag(flag, VFPI_S_BAD_PATTERN);
     return;
   }
+  if (j == i) {
+    set_flag(flag, VFPI_S_NOT_NODAL);
+    return;
+  }
   T R[9];
-  bool fin = true;
+  bool fin = true, neg = true;
   for (int e = 0; e < 9; ++e) {
     R[e] = cval[9 * r0 + e];
     fin &= finite(R[e]);
+    if (nb == 2) {
+      const T x = cval[9 * (r0 + 1) + e];
+      fin &= finite(x);
+      neg &= (x == -R[e]);
+    }
   }
   T ph = phi[m], mm = mu[m];
   fin &= finite(ph) && finite(mm);
   if (!fin) {
     set_flag(flag, VFPI_S_NONFINITE);
+    return;
+  }
+  if (!neg) {
+    set_flag(flag, VFPI_S_NOT_NODAL);
     return;
   }
   if (!(mm >= T(0))) set_flag(flag, VFPI_S_BAD_MU);
@@ -47,8 +71,12 @@ VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict
       err = fmax(err, fabs(d));
     }
   if (!(err <= orth_tol)) set_flag(flag, VFPI_S_NOT_ORTHONORMAL);
-  int old = atomicCAS(cmap + i, -1, (int)m);
-  if (old != -1) set_flag(flag, VFPI_S_SHARED_NODE);
+  if (atomicCAS(cmap + i, -1, (int)m) != -1) set_flag(flag, VFPI_S_SHARED_NODE);
+  if (j >= 0 && atomicCAS(cmap + j, -1, (int)m) != -1) set_flag(flag, VFPI_S_SHARED_NODE);
+  if (cpair) {
+    cpair[2 * m] = (int32_t)i;
+    cpair[2 * m + 1] = (int32_t)j;
+  }
   T* pk = cpack + kPack * m;
   for (int e = 0; e < 9; ++e) pk[e] = R[e];
   pk[9] = ph;
@@ -181,6 +209,44 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
     if (tape_w) tape_w[3 * i + r] = wr[r];
   }
   if (m >= 0) cpack[kPack * (int64_t)m + 11] = (T)(wr[0] + ra.omega);
+}
+
+// D-contact m after the row pass (which grouped each node's 3 DOFs alone):
+// the pair's 6 DOFs share one w-bar (Frobenius: sum a_dd / sum ||A_d*||^2
+// over the six, Sec. IV-C.1), and gamma_m = w_i + w_j (Prop. 3), plus omega.
+// A user W must already be equal on the six DOFs (else BAD_W).
+template <class T>
+VFPI_DEV void pair_setup(int64_t m, const int32_t* __restrict__ cpair, const double* __restrict__ diag,
+                         const double* __restrict__ rn2, const RowsArgs ra, T* __restrict__ w,
+                         double* __restrict__ tape_w, T* __restrict__ cpack, int32_t* flag) {
+  const int64_t i = cpair[2 * m], j = cpair[2 * m + 1];
+  if (i < 0 || j < 0) return;
+  double wi, wj;
+  if (ra.w_mode == VFPI_W_FROBENIUS) {
+    double dn = 0.0, sn = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      dn += diag[3 * i + r];
+      sn += rn2[3 * i + r];
+    }
+    for (int r = 0; r < 3; ++r) {
+      dn += diag[3 * j + r];
+      sn += rn2[3 * j + r];
+    }
+    wi = wj = dn / sn;
+    for (int r = 0; r < 3; ++r) {
+      w[3 * i + r] = (T)wi;
+      w[3 * j + r] = (T)wj;
+      if (tape_w) {
+        tape_w[3 * i + r] = wi;
+        tape_w[3 * j + r] = wj;
+      }
+    }
+  } else {
+    wi = (double)w[3 * i];
+    wj = (double)w[3 * j];
+    if (ra.w_mode == VFPI_W_USER_DIAG && wi != wj) set_flag(flag, VFPI_S_BAD_W);
+  }
+  cpack[kPack * m + 11] = (T)(wi + wj + ra.omega);
 }
 
 }  // namespace vfpi

@@ -30,6 +30,10 @@ struct SweepData {
   T* vprev;               // v^{l-1} per DOF, node-local (nullptr: off)
   double nu, u;
   int first;              // sweep 1: v^0 = v^1
+  // D-contacts: A's block rows in the caller's layout and the contact's nodes
+  const int32_t* col_idx;
+  const T* val;
+  const int32_t* cpair;   // [2 n_c]: i, j (j = -1: S-contact); nullptr: S only
 };
 
 // Chebyshev update of one DOF (identity when d.vprev is null); keeps v^l as the
@@ -83,6 +87,60 @@ VFPI_DEV int contact_step(const T* __restrict__ pk, T vs0, T vs1, T vs2, int pro
   return contact_solve<T>(load_contact<T>(pk), vs0, vs1, vs2, proj, lam, ls);
 }
 
+// v*_x = v_x - W_x (A_x v - b_x) from node x's block row in A's own layout
+// (blocks in row order).  A D-contact needs v* of both of its nodes; each of
+// the two nodes' threads forms both with this one routine, so the two sides
+// compute the same lambda.  w == nullptr: W = alpha I.
+template <class T, bool COH>
+VFPI_DEV void vstar_bsr(const SweepData<T>& a, const T* __restrict__ vcur, const T* w, T alpha, int64_t x,
+                        T vs[3]) {
+  T acc[3] = {T(0), T(0), T(0)};
+  const int64_t r1 = a.row_ptr[x + 1];
+  for (int64_t k = a.row_ptr[x]; k < r1; ++k) {
+    const int64_t c = a.col_idx[k];
+    const T* B = a.val + 9 * k;
+    const T y0 = ldv<COH>(vcur + 3 * c), y1 = ldv<COH>(vcur + 3 * c + 1), y2 = ldv<COH>(vcur + 3 * c + 2);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) acc[r] += B[3 * r] * y0 + B[3 * r + 1] * y1 + B[3 * r + 2] * y2;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T wr = w ? w[3 * x + r] : alpha;
+    vs[r] = ldv<COH>(vcur + 3 * x + r) - wr * (acc[r] - a.b[3 * x + r]);
+  }
+}
+
+// D-contact m (nodes i, j; J_m = [R, -R], eq. jcnode) seen from its node x:
+// lambda* = -(R (v*_i - v*_j) + phi e1) / gamma, projected (Alg. 2), and x's
+// own v* and update v*_x +- W_x R^T lambda.  g > 0 overrides gamma_m, w ==
+// nullptr means W = alpha I.  Returns true when x is node i (which reports
+// lambda, the tape entries and the branch count).
+template <class T, bool COH>
+VFPI_DEV bool dcontact_node(const SweepData<T>& a, const T* __restrict__ vcur, const T* w, T alpha, T g, int64_t x,
+                            int m, T vs_own[3], T vn_own[3], T lam[3], T ls[3], int& br) {
+  const int64_t i = a.cpair[2 * (int64_t)m], j = a.cpair[2 * (int64_t)m + 1];
+  T vi[3], vj[3];
+  vstar_bsr<T, COH>(a, vcur, w, alpha, i, vi);
+  vstar_bsr<T, COH>(a, vcur, w, alpha, j, vj);
+  ContactRec<T> cr = load_contact<T>(a.cpack + kPack * (int64_t)m);
+  if (g > T(0)) cr.g = g;
+  br = contact_solve<T>(cr, vi[0] - vj[0], vi[1] - vj[1], vi[2] - vj[2], a.proj, lam, ls);
+  const bool first = (x == i);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
+    const T wr = w ? w[3 * x + r] : alpha;
+    vs_own[r] = first ? vi[r] : vj[r];
+    vn_own[r] = first ? vs_own[r] + wr * F : vs_own[r] - wr * F;
+  }
+  return first;
+}
+
+template <class T>
+VFPI_DEV bool is_dcontact(const SweepData<T>& a, int m) {
+  return a.cpair && a.cpair[2 * (int64_t)m + 1] >= 0;
+}
+
 // Thread = node (all three rows).  Every lane of the wave calls; cnt may be 0.
 template <class T, bool COH = false, int U = 4>
 VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur, T* __restrict__ vnext,
@@ -102,7 +160,19 @@ VFPI_DEV void sweep_chunk_node(const SweepData<T>& a, const T* __restrict__ vcur
   }
   T vn[3] = {vs[0], vs[1], vs[2]};
   const int m = a.cmap[i];
-  if (m >= 0) {
+  if (m >= 0 && is_dcontact(a, m)) {
+    T lam[3], ls[3];
+    int br;
+    if (dcontact_node<T, COH>(a, vcur, a.w, T(0), T(0), i, m, vs, vn, lam, ls, br)) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        a.lambda[3 * (int64_t)m + r] = lam[r];
+        if (a.tape_lamstar) a.tape_lamstar[3 * (int64_t)m + r] = (double)ls[r];
+      }
+      if (a.tape_branch) a.tape_branch[m] = br;
+      cb[br] += 1;
+    }
+  } else if (m >= 0) {
     const T* pk = a.cpack + kPack * (int64_t)m;
     T lam[3], ls[3];
     int br = contact_step<T>(pk, vs[0], vs[1], vs[2], a.proj, lam, ls);
@@ -146,7 +216,20 @@ VFPI_DEV void sweep_chunk_row(const SweepData<T>& a, const T* __restrict__ vcur,
   if (!act) return;
   T vn = vs;
   const int m = a.cmap[i];
-  if (m >= 0) {
+  if (m >= 0 && is_dcontact(a, m)) {
+    T lam[3], ls[3], vs3[3], vn3[3];
+    int br;
+    const bool first = dcontact_node<T, COH>(a, vcur, a.w, T(0), T(0), i, m, vs3, vn3, lam, ls, br);
+    vn = vn3[r];
+    if (first) {
+      a.lambda[3 * (int64_t)m + r] = lam[r];
+      if (a.tape_lamstar) a.tape_lamstar[3 * (int64_t)m + r] = (double)ls[r];
+      if (r == 0) {
+        if (a.tape_branch) a.tape_branch[m] = br;
+        cb[br] += 1;
+      }
+    }
+  } else if (m >= 0) {
     const T* pk = a.cpack + kPack * (int64_t)m;
     T lam[3], ls[3];
     int br = contact_step<T>(pk, s_vs[0][lane], s_vs[1][lane], s_vs[2][lane], a.proj, lam, ls);

@@ -11,7 +11,7 @@ iteration.  Scenes are described in ``scenes.cloth``, ``scenes.fem`` and
 """
 from .problem import Problem, concat_problems, rng
 from .geometry import onb_duff, contacts_from_gaps
-from .cloth import ClothScene, cloth_cfg1, cloth_cfg2, cloth_cfg4_envs, cloth_cfg5_scene
+from .cloth import ClothScene, cloth_cfg1, cloth_cfg2, cloth_cfg4_envs, cloth_cfg5_scene, cloth_pair_collision
 from .fem import FemScene, fem_cfg3, fem_ctx
 from .random import random_problem, inclined_plane_particles, two_level_diagonal, colliding_particle_pairs
 

@@ -213,3 +213,33 @@ def cloth_cfg5_scene(seed: int = 0, side: int = 64):
     x[:, :2] += g.uniform(-1e-3, 1e-3, size=(sc.n_nodes, 2))
     v = g.normal(0.0, 0.05, size=(sc.n_nodes, 3))
     return sc, x, v
+
+
+def cloth_pair_collision(seed: int = 0, side: int = 32, speed: float = 0.3):
+    """Two equal cloth sheets meeting in free fall (no obstacles): the lower
+    one at z = 0 moving up, the upper one a few mm above moving down, with
+    +-1 mm x/y jitter.  Every upper node within the 5 mm margin of the lower
+    node under it is in a D-contact with it (normal +z, R on the upper node,
+    -R on the lower one, phi = gap / h, mu = 0.5).  Returns the Problem over
+    both sheets (lower sheet first)."""
+    g = rng(f"cloth_pair{side}", seed, "state")
+    sc = ClothScene(side=side)
+    n = sc.n_nodes
+    xl = sc.rest_positions(0.0)
+    xu = sc.rest_positions(0.0)
+    xu[:, :2] += g.uniform(-1e-3, 1e-3, size=(n, 2))
+    xu[:, 2] = g.uniform(1e-3, 7e-3, size=n)
+    vl = np.tile([0.0, 0.0, speed], (n, 1)) + g.normal(size=(n, 3)) * 0.02
+    vu = np.tile([0.0, 0.0, -speed], (n, 1)) + g.normal(size=(n, 3)) * 0.02
+    pl = sc.assemble(xl, vl, with_contacts=False)
+    pu = sc.assemble(xu, vu, with_contacts=False)
+    gap = xu[:, 2] - xl[:, 2]
+    hit = np.nonzero(gap <= sc.delta)[0]
+    from .geometry import onb_duff
+    R = onb_duff(np.tile([0.0, 0.0, 1.0], (hit.shape[0], 1)))
+    row_ptr = np.concatenate([pl.row_ptr, pl.row_ptr[-1] + pu.row_ptr[1:]])
+    return Problem(
+        n_nodes=2 * n, row_ptr=row_ptr, col_idx=np.concatenate([pl.col_idx, pu.col_idx + n]),
+        val=np.concatenate([pl.val, pu.val]), b=np.concatenate([pl.b, pu.b]), v0=np.concatenate([pl.v0, pu.v0]),
+        c_node=n + hit, c_node_j=hit, R=R, phi=gap[hit] / sc.h, mu=np.full(hit.shape[0], 0.5),
+        meta={"scene": "cloth_pair", "side": side, "seed": seed})

@@ -170,11 +170,6 @@ def test_device_detected_data_errors():
 
 
 def test_synchronous_argument_errors():
-    p = scenes.random_problem(50, 10, 4, n_d_contacts=3)
-    s = vf.Solver(50, p.nnzb, 10)
-    A, Jc, b, v = upload(p)
-    with pytest.raises(vf.VfpiError, match="not supported"):
-        s.step(A, b, Jc, v)
     small = vf.Solver(10, 10, 1)
     p2 = scenes.random_problem(50, 5, 4)
     A, Jc, b, v = upload(p2)

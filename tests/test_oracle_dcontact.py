@@ -108,3 +108,13 @@ def test_d_contacts_match_mode_enumeration_and_pgs(seed):
         err = min(np.abs(lam - s).max() for s, _ in sols)
         assert err <= 1e-8 * max(1.0, np.abs(lam).max())
     np.testing.assert_allclose(r["v"], vf + Y @ r["lam"].ravel(), atol=1e-8)
+
+
+def test_cloth_pair_collision_conserves_momentum():
+    """Two sheets meeting in free fall: springs and D-contacts are internal,
+    so at the fixed point sum_i (A v - b)_i = 0 (per axis)."""
+    p = scenes.cloth_pair_collision(0, side=16)
+    r = oracle.vfpi(p, max_iters=20000, tol=1e-13)
+    assert r["iters"] < 20000 and np.count_nonzero(r["branch"]) > 10
+    res = (system_matrix(p) @ r["v"] - p.b).reshape(-1, 3).sum(0)
+    assert np.abs(res).max() <= 1e-10 * np.abs(p.b).max()
