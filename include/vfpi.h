@@ -58,7 +58,7 @@ extern "C" {
 #define VFPI_S_CONVERGED        0x000  /* theta < tol at the break            */
 #define VFPI_S_MAXITER          0x001  /* stopped at max_iters (or fixed_iters) */
 #define VFPI_S_NONFINITE        0x010  /* NaN/Inf in A, b, v, R, phi or mu     */
-#define VFPI_S_NOT_NODAL        0x020  /* J_c row is not one block (S-contact) */
+#define VFPI_S_NOT_NODAL        0x020  /* J_c row is neither [R] nor [R, -R]      */
 #define VFPI_S_NOT_ORTHONORMAL  0x040  /* max |R R^T - I| > 1e-10 (1e-5 in FP32) */
 #define VFPI_S_SHARED_NODE      0x080  /* a node carries two contacts (Prop. 3)  */
 #define VFPI_S_NONPOS_DIAG      0x100  /* a_ii <= 0 or no diagonal block        */
@@ -98,11 +98,14 @@ typedef struct {
 } vfpi_bsr;
 
 /* Nodal contact Jacobian J_c (eq. jcnode) in the same block-row form, one
- * block row per contact: this build solves S-contacts, i.e. rows holding one
- * block R_m in SO(3) (row 0 = contact normal, rows 1-2 = tangents) at the
- * contact's node.  phi[n_contacts] is the normal offset term and
- * mu[n_contacts] >= 0 the friction coefficient (eq. scc).  At most one
- * contact per node.  Element type as for vfpi_bsr.val. */
+ * block row per contact: an S-contact (node against the static environment)
+ * is one block R_m in SO(3) (row 0 = contact normal, rows 1-2 = tangents) at
+ * the contact's node i; a D-contact (node against node) is R_m at node i
+ * followed by -R_m (bitwise the negation) at node j != i, the relative
+ * velocity R_m (v_i - v_j) having its normal along row 0.  phi[n_contacts] is
+ * the normal offset term and mu[n_contacts] >= 0 the friction coefficient
+ * (eq. scc).  At most one contact per node (either node of a D-contact
+ * counts).  Element type as for vfpi_bsr.val. */
 typedef struct {
   int32_t n_contacts;
   int32_t nnzb;
@@ -169,9 +172,9 @@ int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts);
  *   stats   device vfpi_stats, written at the end
  *   tape    NULL, or a device buffer of vfpi_tape_bytes(N, n_c) bytes that
  *           receives what vfpi_step_backward needs
- * Errors: VFPI_E_NULL, VFPI_E_SHAPE, VFPI_E_OPTS, VFPI_E_CAPACITY,
- * VFPI_E_UNSUPPORTED (a J_c row with two blocks: D-contacts; BB modes with
- * Chebyshev or with launch kinds other than 1 and 3), VFPI_E_HIP. */
+ * Errors: VFPI_E_NULL, VFPI_E_SHAPE (also Jc->nnzb > 2 n_c), VFPI_E_OPTS,
+ * VFPI_E_CAPACITY, VFPI_E_UNSUPPORTED (BB modes with Chebyshev or with launch
+ * kinds other than 1 and 3), VFPI_E_HIP. */
 int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc,
               double* v, double* lambda, const vfpi_opts* opts, vfpi_stats* stats,
               void* tape, hipStream_t stream);
@@ -209,6 +212,38 @@ int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc
                        const void* tape, const double* grad_v, const double* grad_lambda,
                        double* grad_b, double* grad_A_val, double* grad_phi, double* grad_mu,
                        const vfpi_opts* opts, vfpi_stats* stats, hipStream_t stream);
+
+/* ---- virtual nodes (Sec. III-A, eq. vforce, eq. vnode) ------------------
+ * A contact at a point that is not a node (a point of a triangle, of a rigid
+ * body) gets a temporary virtual node q tied to the point's velocity J_v v_o
+ * by the viscous force -k_v (J_v v_o - v_q).  The solver then runs on
+ *   A = [A_o + k_v J_v^T J_v, -k_v J_v^T; -k_v J_v, k_v I],  b = [b_o; 0]
+ * (SPD, Prop. 1), whose solution approaches the original contact problem as
+ * k_v grows (Prop. 2).  Virtual node q is node n_o + q of the result; contacts
+ * on it are ordinary S- or D-contacts in that numbering.
+ * J_v: n_v block rows (jv_ptr[n_v+1], jv_col = original node of each 3x3
+ * block, jv_val[9 nnz] row-major), distinct columns within a row.  A_o's rows
+ * must have sorted column indices.
+ *
+ * vfpi_vnode_pattern (host arrays, no device access): block pattern of A,
+ * rows sorted by column, the virtual columns last in each original row.
+ * With aug_col_idx == NULL only aug_row_ptr[n_o+n_v+1] and *aug_nnzb are
+ * written (size query).  Errors: VFPI_E_NULL, VFPI_E_SHAPE (an index out of
+ * range, decreasing offsets, a repeated column in a J_v row),
+ * VFPI_E_CAPACITY (more than cap blocks). */
+int vfpi_vnode_pattern(int32_t n_o, const int32_t* row_ptr, const int32_t* col_idx, int32_t n_v,
+                       const int32_t* jv_ptr, const int32_t* jv_col, int32_t* aug_row_ptr,
+                       int32_t* aug_col_idx, int64_t cap, int64_t* aug_nnzb);
+
+/* vfpi_vnode_values (device arrays, FP64, asynchronous on `stream`): the
+ * block values of A on the pattern from vfpi_vnode_pattern (copied to the
+ * device), b = [b_o; 0] and the warm start v = [v_o; J_v v_o].
+ * Errors: VFPI_E_NULL, VFPI_E_SHAPE, VFPI_E_OPTS (k_v not positive and
+ * finite), VFPI_E_HIP. */
+int vfpi_vnode_values(const vfpi_bsr* A_o, const double* b_o, const double* v_o, int32_t n_v,
+                      const int32_t* jv_ptr, const int32_t* jv_col, const double* jv_val, double k_v,
+                      const int32_t* aug_row_ptr, const int32_t* aug_col_idx, double* aug_val,
+                      double* b, double* v, hipStream_t stream);
 
 /* Profiling aid.  While enabled on a context, vfpi_step, vfpi_step_batched
  * and vfpi_step_backward record HIP events on their stream before the setup

@@ -39,7 +39,8 @@ VFPI_PROJ_STRICT = 0
 VFPI_PROJ_PROXIMAL = 1
 
 ENTRY_POINTS = ("vfpi_create", "vfpi_destroy", "vfpi_tape_bytes", "vfpi_step", "vfpi_step_batched",
-                "vfpi_step_backward", "vfpi_timing_enable", "vfpi_timing_read", "vfpi_error_string")
+                "vfpi_step_backward", "vfpi_vnode_pattern", "vfpi_vnode_values", "vfpi_timing_enable",
+                "vfpi_timing_read", "vfpi_error_string")
 
 
 class vfpi_bsr(ctypes.Structure):
@@ -98,6 +99,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vfpi_step_backward.argtypes = [P, ctypes.POINTER(vfpi_bsr), ctypes.POINTER(vfpi_contacts), P, P, P, P, P,
                                        P, P, ctypes.POINTER(vfpi_opts), P, P]
     lib.vfpi_step_backward.restype = ctypes.c_int
+    lib.vfpi_vnode_pattern.argtypes = [I32, P, P, I32, P, P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.vfpi_vnode_pattern.restype = ctypes.c_int
+    lib.vfpi_vnode_values.argtypes = [ctypes.POINTER(vfpi_bsr), P, P, I32, P, P, P, ctypes.c_double, P, P, P, P, P,
+                                      P]
+    lib.vfpi_vnode_values.restype = ctypes.c_int
     lib.vfpi_timing_enable.argtypes = [P, I32]
     lib.vfpi_timing_enable.restype = ctypes.c_int
     lib.vfpi_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
@@ -155,6 +161,20 @@ def vfpi_step_backward(ctx, A: vfpi_bsr, Jc: vfpi_contacts, tape, grad_v, grad_l
                        grad_phi, grad_mu, opts: vfpi_opts, stats, stream) -> int:
     return load().vfpi_step_backward(ctx, ctypes.byref(A), ctypes.byref(Jc), tape, grad_v, grad_lambda, grad_b,
                                      grad_A_val, grad_phi, grad_mu, ctypes.byref(opts), stats, stream)
+
+
+def vfpi_vnode_pattern(n_o, row_ptr, col_idx, n_v, jv_ptr, jv_col, aug_row_ptr, aug_col_idx, cap) -> int:
+    """Host arrays (pointers as ints); returns the number of blocks."""
+    nnz = ctypes.c_int64()
+    check(load().vfpi_vnode_pattern(n_o, row_ptr, col_idx, n_v, jv_ptr, jv_col, aug_row_ptr, aug_col_idx, cap,
+                                    ctypes.byref(nnz)), "vfpi_vnode_pattern")
+    return nnz.value
+
+
+def vfpi_vnode_values(A_o: vfpi_bsr, b_o, v_o, n_v, jv_ptr, jv_col, jv_val, k_v, aug_row_ptr, aug_col_idx, aug_val,
+                      b, v, stream) -> int:
+    return load().vfpi_vnode_values(ctypes.byref(A_o), b_o, v_o, n_v, jv_ptr, jv_col, jv_val, float(k_v),
+                                    aug_row_ptr, aug_col_idx, aug_val, b, v, stream)
 
 
 def vfpi_timing_enable(ctx, on: bool) -> None:

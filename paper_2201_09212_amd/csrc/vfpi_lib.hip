@@ -4,3 +4,4 @@
 #include "forward.hip"
 #include "batched.hip"
 #include "adjoint.hip"
+#include "vnode.hip"

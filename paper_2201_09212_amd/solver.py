@@ -183,3 +183,40 @@ class Solver:
                                      stream_handle(stream))
         _abi.check(rc, "vfpi_step_backward")
         return {"b": gb, "A": gA, "phi": gphi, "mu": gmu, "stats": stats}
+
+
+def vnode_augment(A_o: Bsr, b_o, v_o, jv_ptr, jv_col, jv_val, k_v, stream=None):
+    """System of eq. vnode for virtual nodes tied to the points J_v v_o with
+    gain k_v: returns (A, b, v) over n_o + n_v nodes (virtual node q is node
+    n_o + q).  The block pattern comes from ``vfpi_vnode_pattern`` on host
+    copies of the index arrays, the values from ``vfpi_vnode_values`` on the
+    device."""
+    dev = b_o.device
+    n_o = A_o.n_nodes
+    n_v = int(jv_ptr.numel()) - 1
+    rp_h = A_o.row_ptr.detach().to("cpu", torch.int32).contiguous()
+    ci_h = A_o.col_idx.detach().to("cpu", torch.int32).contiguous()
+    jp_h = jv_ptr.detach().to("cpu", torch.int32).contiguous()
+    jc_h = jv_col.detach().to("cpu", torch.int32).contiguous()
+    g_ptr = torch.empty(n_o + n_v + 1, dtype=torch.int32)
+    nnz = _abi.vfpi_vnode_pattern(n_o, rp_h.data_ptr(), ci_h.data_ptr(), n_v, jp_h.data_ptr(), jc_h.data_ptr(),
+                                  g_ptr.data_ptr(), None, 0)
+    g_col = torch.empty(max(nnz, 1), dtype=torch.int32)
+    _abi.vfpi_vnode_pattern(n_o, rp_h.data_ptr(), ci_h.data_ptr(), n_v, jp_h.data_ptr(), jc_h.data_ptr(),
+                            g_ptr.data_ptr(), g_col.data_ptr(), nnz)
+    rp = g_ptr.to(dev)
+    ci = g_col[:nnz].to(dev)
+    val = torch.empty(9 * max(nnz, 1), dtype=torch.float64, device=dev)
+    n = 3 * (n_o + n_v)
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    v = torch.empty(n, dtype=torch.float64, device=dev)
+    jvp = jv_ptr.to(dev, torch.int32).contiguous()
+    jvc = jv_col.to(dev, torch.int32).contiguous()
+    jvv = jv_val.to(dev, torch.float64).contiguous()
+    _check(b_o, torch.float64, 3 * n_o, "b_o")
+    _check(v_o, torch.float64, 3 * n_o, "v_o")
+    with torch.cuda.device(dev):
+        rc = _abi.vfpi_vnode_values(A_o.desc(), _ptr(b_o), _ptr(v_o), n_v, _ptr(jvp), _ptr(jvc), _ptr(jvv), k_v,
+                                    _ptr(rp), _ptr(ci), _ptr(val), _ptr(b), _ptr(v), stream_handle(stream))
+    _abi.check(rc, "vfpi_vnode_values")
+    return Bsr(n_o + n_v, rp, ci, val[:9 * nnz]), b, v
