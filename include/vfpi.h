@@ -114,6 +114,12 @@ typedef struct {
   const void* val;
   const void* phi;
   const void* mu;
+  const void* mu2;   /* NULL: isotropic friction.  Else [n_contacts] >= 0: anisotropic
+                        friction on the elliptic cone lambda_n^2 >= t1^2/mu^2 + t2^2/mu2^2
+                        (tangents = rows 1, 2 of R; Sec. III-E), solved by the strict
+                        operator, which gives the maximal-dissipation impulse (Prop. 6).
+                        Not with VFPI_PROJ_PROXIMAL nor vfpi_step_backward
+                        (VFPI_E_UNSUPPORTED). */
 } vfpi_contacts;
 
 typedef struct {

@@ -31,7 +31,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .core import (contact_gamma, contact_jacobian, frobenius_w, project_proximal, project_strict, row_stats,
+from .core import (contact_gamma, contact_jacobian, frobenius_w, project_proximal, project_strict,
+                   project_strict_aniso, row_stats,
                    validate)
 
 
@@ -43,6 +44,11 @@ def vfpi_chebyshev(p, *, max_iters=100, tol=0.0, fixed_iters=False, l_s=10, u=1.
     J = contact_jacobian(p)
     nc = p.n_contacts
     project = project_strict if projection == "strict" else project_proximal
+    if getattr(p, "mu2", None) is not None:  # anisotropic friction (strict operator only)
+        assert projection == "strict"
+
+        def project(ls, mu1, _mu2=p.mu2):
+            return project_strict_aniso(ls, mu1, _mu2)
     if w_mode == "frobenius":
         w = frobenius_w(p, *row_stats(A))
     elif w_mode == "scalar":

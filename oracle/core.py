@@ -187,6 +187,48 @@ def project_proximal(lam_star, mu):
     return lam, branch.astype(np.int32)
 
 
+def _ellipse_closest(y1, y2, a, b):
+    """Closest point to (y1, y2) in the ellipse x1^2/a^2 + x2^2/b^2 <= 1 (a, b
+    >= 0; a zero axis makes it a segment).  Outside, the Lagrange condition of
+    min |x - y|^2 gives x_i = a_i^2 y_i / (a_i^2 + s) with s > 0 the root of
+    sum_i (a_i y_i / (a_i^2 + s))^2 = 1; the left side falls from above 1 at
+    s = 0 to at most 1 at s = a |y1| + b |y2|, and brentq brackets it there."""
+    from scipy.optimize import brentq
+
+    if a == 0.0 or b == 0.0:
+        x1, x2 = min(max(y1, -a), a), min(max(y2, -b), b)
+        return x1, x2, (x1 == y1 and x2 == y2)
+    if (y1 * b) ** 2 + (y2 * a) ** 2 <= (a * b) ** 2:
+        return y1, y2, True
+
+    def F(s):
+        return (a * y1 / (a * a + s)) ** 2 + (b * y2 / (b * b + s)) ** 2 - 1.0
+
+    s = brentq(F, 0.0, a * abs(y1) + b * abs(y2), xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+    return a * a * y1 / (a * a + s), b * b * y2 / (b * b + s), False
+
+
+def project_strict_aniso(lam_star, mu1, mu2):
+    """Strict ProjectFC for the elliptic friction cone of Sec. III-E
+    (anisotropic friction, lambda_n^2 >= t1^2/mu1^2 + t2^2/mu2^2):
+    lambda_n = max(lambda*_n, 0) and lambda_t = the closest point to
+    lambda*_t in the ellipse of semi-axes mu1 lambda_n, mu2 lambda_n, which is
+    the maximal-dissipation solution of the contact's surrogate problem
+    (Prop. 6).  Branches as in project_strict."""
+    lam_star = np.asarray(lam_star, dtype=np.float64)
+    nc = lam_star.shape[0]
+    lam = np.zeros((nc, 3))
+    branch = np.full(nc, BRANCH_OPEN, dtype=np.int32)
+    for m in range(nc):
+        n = lam_star[m, 0]
+        if n <= 0.0:
+            continue
+        x1, x2, inside = _ellipse_closest(lam_star[m, 1], lam_star[m, 2], mu1[m] * n, mu2[m] * n)
+        lam[m] = (n, x1, x2)
+        branch[m] = BRANCH_STICK if inside else BRANCH_SLIP
+    return lam, branch
+
+
 def gershgorin_alpha(A):
     return 1.0 / np.asarray(abs(A).sum(axis=1)).max()
 
@@ -208,6 +250,13 @@ def vfpi(p, *, max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_
     J = contact_jacobian(p)
     n, nc = p.n, p.n_contacts
     project = project_strict if projection == "strict" else project_proximal
+    mu2 = getattr(p, "mu2", None)
+    if mu2 is not None:  # anisotropic friction: strict operator on the elliptic cone
+        if projection != "strict":
+            raise ValueError("anisotropic friction is defined with the strict operator (Prop. 6)")
+
+        def project(ls, mu1, _mu2=mu2):
+            return project_strict_aniso(ls, mu1, _mu2)
     alpha = None
     if w_mode == "frobenius":
         diag, rn2 = row_stats(A) if stats is None else stats

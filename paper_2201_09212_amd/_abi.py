@@ -51,7 +51,7 @@ class vfpi_bsr(ctypes.Structure):
 class vfpi_contacts(ctypes.Structure):
     _fields_ = [("n_contacts", ctypes.c_int32), ("nnzb", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("phi", ctypes.c_void_p),
-                ("mu", ctypes.c_void_p)]
+                ("mu", ctypes.c_void_p), ("mu2", ctypes.c_void_p)]
 
 
 class vfpi_opts(ctypes.Structure):

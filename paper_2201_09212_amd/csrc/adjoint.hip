@@ -348,6 +348,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
   if (opts->max_iters < 0 || !(opts->tol >= 0.0)) return VFPI_E_OPTS;
   if (opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
+  if (Jc->mu2) return VFPI_E_UNSUPPORTED;  // anisotropic friction: no projection Jacobian here
   if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
   if (N == 0) {
     hipLaunchKernelGGL(k_stats_empty, dim3(1), dim3(1), 0, stream, stats);
@@ -365,7 +366,8 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
-                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->cpair, ctx->flags, 1e-10);
+                       static_cast<const double*>(Jc->mu), nullptr, N, ctx->cmap, cpack, ctx->cpair, ctx->flags,
+                       1e-10);
   // W comes from the forward tape; the row pass rebuilds the interleaved copy of A.
   RowsArgs ra;
   ra.nnzb = A->nnzb;

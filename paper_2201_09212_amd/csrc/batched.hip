@@ -30,6 +30,7 @@ struct BatchArgs {
   const float* cval;
   const float* phi;
   const float* mu;
+  const float* mu2;    // nullable: anisotropic friction
   int32_t nnzb_c;
   int32_t* scol;
   float* sval;
@@ -100,8 +101,8 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
     for (int64_t i = n_lo + threadIdx.x; i < n_hi; i += blockDim.x) a.cmap[i] = -1;
     __syncthreads();
     for (int64_t m = m_lo + threadIdx.x; m < m_hi; m += blockDim.x)
-      contact_setup<float>(m, a.nnzb_c, a.crp, a.ccol, a.cval, a.phi, a.mu, n_lo, n_hi, a.cmap, a.cpack, a.cpair,
-                           &s_flag, 1e-5);
+      contact_setup<float>(m, a.nnzb_c, a.crp, a.ccol, a.cval, a.phi, a.mu, a.mu2, n_lo, n_hi, a.cmap, a.cpack,
+                           a.cpair, &s_flag, 1e-5);
     __syncthreads();
     const int64_t nn = n_hi - n_lo;
     const int64_t nch = (nn + 63) / 64;
@@ -242,6 +243,7 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   int rc = vfpi_check_opts(opts, true);
   if (rc) return rc;
   if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
+  if (Jc->mu2 && opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
   if (n_env == 0) return VFPI_OK;
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -263,6 +265,7 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   ba.cval = static_cast<const float*>(Jc->val);
   ba.phi = static_cast<const float*>(Jc->phi);
   ba.mu = static_cast<const float*>(Jc->mu);
+  ba.mu2 = static_cast<const float*>(Jc->mu2);
   ba.nnzb_c = Jc->nnzb;
   ba.scol = ctx->scol;
   ba.sval = static_cast<float*>(ctx->sval);

@@ -24,7 +24,7 @@ namespace vfpi {
 enum { BR_OPEN = 0, BR_STICK = 1, BR_SLIP = 2 };
 
 constexpr int kWave = 64;
-constexpr int kPack = 12;  // per-contact record: R (9), phi, mu, gamma
+constexpr int kPack = 13;  // per-contact record: R (9), phi, mu, gamma, mu2
 constexpr int kMaxGridSlots = 1024;  // workgroups of a persistent launch (slots per parity)
 // Slot memory of the grid reductions: region 0 = [2][kMaxGridSlots] for the
 // residual / barrier; region 1 = [2][3][kMaxGridSlots] for the three dot
@@ -101,9 +101,52 @@ VFPI_DEV int project_proximal(T& n, T& t1, T& t2, T mu) {
   return BR_SLIP;
 }
 
+// Strict operator on the elliptic cone t1^2/mu1^2 + t2^2/mu2^2 <= lambda_n^2
+// (anisotropic friction, Sec. III-E): lambda_t = the closest point to t in the
+// ellipse of semi-axes a = mu1 lambda_n, b = mu2 lambda_n, which is the
+// maximal-dissipation answer (Prop. 6).  Outside it, x_i = a_i^2 t_i / (a_i^2
+// + s) with s > 0 the root of F(s) = sum_i a_i^2 t_i^2 / (a_i^2 + s)^2 - 1.
+// F is convex and decreasing for s > -min(a^2, b^2) and F(0) > 0, so Newton
+// from s = 0 climbs monotonically to the root; it stops when a step no longer
+// increases s.  A zero semi-axis makes the ellipse a segment (clamp).
 template <class T>
-VFPI_DEV int project(int mode, T& n, T& t1, T& t2, T mu) {
-  return mode == VFPI_PROJ_PROXIMAL ? project_proximal(n, t1, t2, mu) : project_strict(n, t1, t2, mu);
+VFPI_DEV int project_ellipse(T& n, T& t1, T& t2, T mu1, T mu2) {
+  if (!(n > T(0))) {
+    n = t1 = t2 = T(0);
+    return BR_OPEN;
+  }
+  const T a = mu1 * n, b = mu2 * n;
+  if (a == T(0) || b == T(0)) {
+    const T x1 = fmin(fmax(t1, -a), a), x2 = fmin(fmax(t2, -b), b);
+    const bool in = (x1 == t1) && (x2 == t2);
+    t1 = x1;
+    t2 = x2;
+    return in ? BR_STICK : BR_SLIP;
+  }
+  const T tb = t1 * b, ta = t2 * a, ab = a * b;
+  if (tb * tb + ta * ta <= ab * ab) return BR_STICK;
+  const T a2 = a * a, b2 = b * b, c1 = a2 * t1 * t1, c2 = b2 * t2 * t2;
+  T s = T(0);
+  for (int it = 0; it < 200; ++it) {
+    const T d1 = a2 + s, d2 = b2 + s;
+    const T f1 = c1 / (d1 * d1), f2 = c2 / (d2 * d2);
+    const T F = f1 + f2 - T(1);
+    const T dF = T(-2) * (f1 / d1 + f2 / d2);
+    const T sn = s - F / dF;
+    if (!(sn > s)) break;
+    s = sn;
+  }
+  t1 = a2 * t1 / (a2 + s);
+  t2 = b2 * t2 / (b2 + s);
+  return BR_SLIP;
+}
+
+// mu2 != mu selects the anisotropic strict operator (the caller refuses it
+// with the proximal operator).
+template <class T>
+VFPI_DEV int project(int mode, T& n, T& t1, T& t2, T mu, T mu2) {
+  if (mode == VFPI_PROJ_PROXIMAL) return project_proximal(n, t1, t2, mu);
+  return (mu2 != mu) ? project_ellipse(n, t1, t2, mu, mu2) : project_strict(n, t1, t2, mu);
 }
 
 // ---- chunk-interleaved copy of one chunk's block rows ------------------

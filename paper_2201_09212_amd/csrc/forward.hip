@@ -38,11 +38,11 @@ __global__ void k_stats_empty(vfpi_stats* st) {
 
 template <class T>
 __global__ void k_contacts(int32_t nc, int32_t nnzb_c, const int32_t* crp, const int32_t* ccol, const T* cval,
-                           const T* phi, const T* mu, int32_t n_nodes, int32_t* cmap, T* cpack, int32_t* cpair,
-                           int32_t* flags, double orth_tol) {
+                           const T* phi, const T* mu, const T* mu2, int32_t n_nodes, int32_t* cmap, T* cpack,
+                           int32_t* cpair, int32_t* flags, double orth_tol) {
   int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (m < nc)
-    contact_setup<T>(m, nnzb_c, crp, ccol, cval, phi, mu, 0, n_nodes, cmap, cpack, cpair, flags, orth_tol);
+    contact_setup<T>(m, nnzb_c, crp, ccol, cval, phi, mu, mu2, 0, n_nodes, cmap, cpack, cpair, flags, orth_tol);
 }
 
 // Shared W and gamma of every D-contact pair (after the row pass).
@@ -633,6 +633,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   if (rc) return rc;
   const bool bb = opts->w_mode == VFPI_W_BB1 || opts->w_mode == VFPI_W_BB2;
   if (bb && opts->cheby_ls > 0) return VFPI_E_UNSUPPORTED;
+  if (Jc->mu2 && opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
   if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;  // at most two blocks per contact row
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
   if (N == 0) {
@@ -653,7 +654,8 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
-                       static_cast<const double*>(Jc->mu), N, ctx->cmap, cpack, ctx->cpair, ctx->flags, 1e-10);
+                       static_cast<const double*>(Jc->mu), static_cast<const double*>(Jc->mu2), N, ctx->cmap,
+                       cpack, ctx->cpair, ctx->flags, 1e-10);
   RowsArgs ra;
   ra.nnzb = A->nnzb;
   ra.w_mode = opts->w_mode;

@@ -18,7 +18,8 @@ namespace vfpi {
 template <class T>
 VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict__ crp,
                             const int32_t* __restrict__ ccol, const T* __restrict__ cval,
-                            const T* __restrict__ phi, const T* __restrict__ mu, int64_t node_lo,
+                            const T* __restrict__ phi, const T* __restrict__ mu, const T* __restrict__ mu2,
+                            int64_t node_lo,
                             int64_t node_hi, int32_t* cmap, T* cpack, int32_t* cpair, int32_t* flag,
                             double orth_tol) {
   if (cpair) {  // a rejected row must not leave a stale pair behind
@@ -52,8 +53,8 @@ VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict
       neg &= (x == -R[e]);
     }
   }
-  T ph = phi[m], mm = mu[m];
-  fin &= finite(ph) && finite(mm);
+  T ph = phi[m], mm = mu[m], m2 = mu2 ? mu2[m] : mu[m];
+  fin &= finite(ph) && finite(mm) && finite(m2);
   if (!fin) {
     set_flag(flag, VFPI_S_NONFINITE);
     return;
@@ -62,7 +63,7 @@ VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict
     set_flag(flag, VFPI_S_NOT_NODAL);
     return;
   }
-  if (!(mm >= T(0))) set_flag(flag, VFPI_S_BAD_MU);
+  if (!(mm >= T(0)) || !(m2 >= T(0))) set_flag(flag, VFPI_S_BAD_MU);
   double err = 0.0;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
@@ -81,6 +82,7 @@ VFPI_DEV void contact_setup(int64_t m, int32_t nnzb_c, const int32_t* __restrict
   for (int e = 0; e < 9; ++e) pk[e] = R[e];
   pk[9] = ph;
   pk[10] = mm;
+  pk[12] = m2;
 }
 
 struct RowsArgs {

@@ -46,11 +46,12 @@ VFPI_DEV T cheby_update(const SweepData<T>& a, int64_t k, T vss, T v) {
   return (T)a.nu * ((T)a.u * (vss - v) + v - vp) + vp;
 }
 
-// One contact's packed record: R (row 0 = normal), phi, mu, gamma.
+// One contact's packed record: R (row 0 = normal), phi, mu, gamma, mu2
+// (friction along tangent 2; equal to mu unless friction is anisotropic).
 template <class T>
 struct ContactRec {
   T R[9];
-  T phi, mu, g;
+  T phi, mu, g, mu2;
 };
 
 template <class T>
@@ -61,6 +62,7 @@ VFPI_DEV ContactRec<T> load_contact(const T* __restrict__ pk) {
   c.phi = pk[9];
   c.mu = pk[10];
   c.g = pk[11];
+  c.mu2 = pk[12];
   return c;
 }
 
@@ -69,7 +71,7 @@ VFPI_DEV ContactRec<T> load_contact(const T* __restrict__ pk) {
 template <class T>
 VFPI_DEV int contact_solve(const ContactRec<T>& cr, T vs0, T vs1, T vs2, int proj, T lam[3], T ls[3]) {
   const T* R = cr.R;
-  const T phi = cr.phi, mu = cr.mu, g = cr.g;
+  const T phi = cr.phi, mu = cr.mu, g = cr.g, mu2 = cr.mu2;
   const T e0 = R[0] * vs0 + R[1] * vs1 + R[2] * vs2;
   const T e1 = R[3] * vs0 + R[4] * vs1 + R[5] * vs2;
   const T e2 = R[6] * vs0 + R[7] * vs1 + R[8] * vs2;
@@ -79,7 +81,7 @@ VFPI_DEV int contact_solve(const ContactRec<T>& cr, T vs0, T vs1, T vs2, int pro
   lam[0] = ls[0];
   lam[1] = ls[1];
   lam[2] = ls[2];
-  return project(proj, lam[0], lam[1], lam[2], mu);
+  return project(proj, lam[0], lam[1], lam[2], mu, mu2);
 }
 
 template <class T>

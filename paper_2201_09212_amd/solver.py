@@ -60,12 +60,15 @@ class Contacts:
     val: torch.Tensor
     phi: torch.Tensor
     mu: torch.Tensor
+    mu2: torch.Tensor | None = None  # anisotropic friction (tangent 2); None: isotropic
 
     def desc(self):
         _check(self.row_ptr, torch.int32, self.n_contacts + 1, "Jc.row_ptr")
         nnzb = int(self.col_idx.numel())
+        if self.mu2 is not None and (self.mu2.numel() != self.n_contacts or self.mu2.dtype != self.mu.dtype):
+            raise ValueError("mu2 must match mu")
         return _abi.vfpi_contacts(self.n_contacts, nnzb, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.val),
-                                  _ptr(self.phi), _ptr(self.mu))
+                                  _ptr(self.phi), _ptr(self.mu), _ptr(self.mu2))
 
 
 def bsr_from_arrays(n_nodes, row_ptr, col_idx, val, dtype=torch.float64, device=None) -> Bsr:
@@ -75,14 +78,16 @@ def bsr_from_arrays(n_nodes, row_ptr, col_idx, val, dtype=torch.float64, device=
                torch.as_tensor(np.ascontiguousarray(val).reshape(-1), device=d).to(dtype).contiguous())
 
 
-def contacts_from_arrays(row_ptr, col_idx, val, phi, mu, dtype=torch.float64, device=None) -> Contacts:
+def contacts_from_arrays(row_ptr, col_idx, val, phi, mu, dtype=torch.float64, device=None, mu2=None) -> Contacts:
     d = _dev(device)
     nc = len(row_ptr) - 1
     return Contacts(nc, torch.as_tensor(np.ascontiguousarray(row_ptr, np.int32), device=d),
                     torch.as_tensor(np.ascontiguousarray(col_idx, np.int32), device=d),
                     torch.as_tensor(np.ascontiguousarray(val).reshape(-1), device=d).to(dtype).contiguous(),
                     torch.as_tensor(np.ascontiguousarray(phi), device=d).to(dtype).contiguous(),
-                    torch.as_tensor(np.ascontiguousarray(mu), device=d).to(dtype).contiguous())
+                    torch.as_tensor(np.ascontiguousarray(mu), device=d).to(dtype).contiguous(),
+                    None if mu2 is None else
+                    torch.as_tensor(np.ascontiguousarray(mu2), device=d).to(dtype).contiguous())
 
 
 def make_opts(max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_user=None, alpha=0.0,

@@ -43,6 +43,7 @@ class Problem:
     phi: np.ndarray
     mu: np.ndarray
     meta: dict = dataclasses.field(default_factory=dict)
+    mu2: np.ndarray | None = None  # anisotropic friction: coefficient along tangent 2 (mu along tangent 1)
 
     def __post_init__(self):
         self.row_ptr = np.ascontiguousarray(self.row_ptr, dtype=np.int32)
@@ -55,6 +56,9 @@ class Problem:
         self.R = np.ascontiguousarray(self.R, dtype=np.float64).reshape(-1, 3, 3)
         self.phi = np.ascontiguousarray(self.phi, dtype=np.float64).reshape(-1)
         self.mu = np.ascontiguousarray(self.mu, dtype=np.float64).reshape(-1)
+        if self.mu2 is not None:
+            self.mu2 = np.ascontiguousarray(self.mu2, dtype=np.float64).reshape(-1)
+            assert self.mu2.shape == self.mu.shape
         n = 3 * self.n_nodes
         assert self.row_ptr.shape == (self.n_nodes + 1,)
         assert self.col_idx.shape == (self.nnzb,)
@@ -135,5 +139,7 @@ def concat_problems(problems: list) -> Batch:
         phi=np.concatenate([p.phi for p in problems]),
         mu=np.concatenate([p.mu for p in problems]),
         meta={"batched": True},
+        mu2=(np.concatenate([p.mu if p.mu2 is None else p.mu2 for p in problems])
+             if any(p.mu2 is not None for p in problems) else None),
     )
     return Batch(big, node_off.astype(np.int32), blk_off.astype(np.int32), con_off.astype(np.int32), problems)

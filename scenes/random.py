@@ -49,7 +49,7 @@ def random_problem(n_nodes: int, n_contacts: int, seed: int, *, degree: float = 
                    meta={"scene": "random", "seed": seed})
 
 
-def inclined_plane_particles(alpha, mu, mass=1.0, h=0.01, g=9.81, v_k=None, phi=None) -> Problem:
+def inclined_plane_particles(alpha, mu, mass=1.0, h=0.01, g=9.81, v_k=None, phi=None, mu2=None) -> Problem:
     """Independent particles, each resting on its own inclined plane through the
     origin with normal (sin a, 0, cos a) under gravity (0, 0, -g): A = m I,
     b = m (v_k + h g_vec), one S-contact per particle.  The tangent basis is
@@ -69,7 +69,7 @@ def inclined_plane_particles(alpha, mu, mass=1.0, h=0.01, g=9.81, v_k=None, phi=
                    b=b.reshape(-1), v0=np.asarray(v_k, dtype=np.float64).reshape(-1),
                    c_node=np.arange(n_p), c_node_j=np.full(n_p, -1),
                    R=R, phi=np.zeros(n_p) if phi is None else phi, mu=mu,
-                   meta={"scene": "inclined_plane", "h": h, "g": g})
+                   meta={"scene": "inclined_plane", "h": h, "g": g}, mu2=mu2)
 
 
 def two_level_diagonal(n_nodes: int, seed: int, *, low=1.0, high=4.0, in_low_space=True) -> tuple:

@@ -27,7 +27,7 @@ def upload(p, dtype=torch.float64):
     dev = torch.device("cuda", 0)
     A = vf.bsr_from_arrays(p.n_nodes, p.row_ptr, p.col_idx, p.val, dtype=dtype, device=dev)
     crp, ccol, cval = p.jc_bsr()
-    Jc = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, dtype=dtype, device=dev)
+    Jc = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, dtype=dtype, device=dev, mu2=p.mu2)
     b = torch.as_tensor(p.b, device=dev).to(dtype)
     v = torch.as_tensor(p.v0, device=dev).to(dtype)
     return A, Jc, b, v

@@ -1,0 +1,113 @@
+"""Anisotropic friction (Sec. III-E, elliptic cone, strict operator = MDP by
+Prop. 6) on the GPU vs the FP64 oracle: fixed sweep counts for every launch
+kind (1e-9), the batched FP32 kernel (1e-4), a sliding particle whose path
+curves, and the unsupported combinations."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2201_09212_amd as vf
+import scenes
+from paper_2201_09212_amd import _abi
+from tests.gpu_util import gpu_step, rel, say, solver_for, upload
+from tests.test_gpu_batched import TOL, run_batched
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {"grid_node2": 1 | (2 << 8), "grid_row1": 2 | (1 << 8), "wg1_node16": 3 | (16 << 8), "wg1_row5": 4,
+            "regs2": 5 | (2 << 8), "regs8": 5 | (8 << 8)}
+
+
+def _aniso(p, seed, lo=0.05, hi=1.2):
+    p.mu2 = np.random.default_rng(seed).uniform(lo, hi, p.n_contacts)
+    return p
+
+
+def _problems():
+    yield "random700", _aniso(scenes.random_problem(700, 300, 4, degree=5.0, phi_scale=0.5), 0)
+    yield "random700_d", _aniso(scenes.random_problem(700, 300, 5, degree=5.0, phi_scale=0.5, n_d_contacts=100), 1)
+    sc, x, v = scenes.cloth_cfg2(0)
+    yield "cloth128", _aniso(sc.assemble(x, v), 2)
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_aniso_fixed_sweeps_parity(variant):
+    for name, p in _problems():
+        if name == "cloth128" and variant.startswith("wg1"):
+            continue
+        L = 30
+        ref = oracle.vfpi(p, max_iters=L, fixed_iters=True)
+        v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, variant=VARIANTS[variant])
+        ev, el = rel(v, ref["v"]), rel(lam, ref["lam"])
+        br = np.bincount(ref["branch"], minlength=3)
+        say(f"  {name} {variant}: rel_v={ev:.2e} rel_lam={el:.2e} branches(o/st/sl)={br.tolist()}")
+        assert ev <= 1e-9 and el <= 1e-9
+        assert [st["n_open"], st["n_stick"], st["n_slip"]] == br.tolist()
+
+
+def test_aniso_with_omega_chebyshev_bb():
+    p = _aniso(scenes.random_problem(700, 300, 4, degree=5.0, phi_scale=0.5), 3)
+    from oracle.chebyshev import vfpi_chebyshev
+    L = 30
+    for opts, ref in ((dict(omega=0.05), oracle.vfpi(p, max_iters=L, fixed_iters=True, omega=0.05)),
+                      (dict(cheby_ls=5), vfpi_chebyshev(p, max_iters=L, fixed_iters=True, l_s=5)),
+                      (dict(w_mode="bb1"), oracle.vfpi(p, max_iters=L, fixed_iters=True, w_mode="bb1"))):
+        v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, **opts)
+        say(f"  random700 aniso {opts}: rel_v={rel(v, ref['v']):.2e} rel_lam={rel(lam, ref['lam']):.2e}")
+        assert rel(v, ref["v"]) <= 1e-9 and rel(lam, ref["lam"]) <= 1e-9
+
+
+def test_batched_aniso():
+    envs = [_aniso(scenes.random_problem(n, nc, s, degree=4.0, phi_scale=0.5, n_d_contacts=nd), s)
+            for s, (n, nc, nd) in enumerate([(90, 40, 10), (300, 100, 0), (500, 200, 30)])]
+    envs.append(scenes.random_problem(200, 80, 9, degree=4.0, phi_scale=0.5))  # isotropic env in the batch
+    batch = scenes.concat_problems(envs)
+    L = 30
+    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True)
+    worst = 0.0
+    for e, pe in enumerate(envs):
+        ref = oracle.vfpi(pe, max_iters=L, fixed_iters=True)
+        n0, n1 = batch.env_node_off[e], batch.env_node_off[e + 1]
+        m0, m1 = batch.env_con_off[e], batch.env_con_off[e + 1]
+        worst = max(worst, rel(v[3 * n0:3 * n1], ref["v"]), rel(lam[3 * m0:3 * m1], ref["lam"]))
+    say(f"  batched aniso: worst rel {worst:.2e}")
+    assert worst <= TOL
+
+
+def test_sliding_particle_path_curves():
+    """A particle sliding on a plane with mu1 != mu2: every step the GPU
+    matches the oracle, and the velocity direction turns (towards the
+    low-friction axis), unlike with isotropic friction."""
+    m, h, g = 1.0, 0.01, 9.81
+    v = np.array([[1.0, 1.0, 0.0]])
+    mu1, mu2 = 0.1, 0.6
+    angles = []
+    for step in range(30):
+        p = scenes.inclined_plane_particles([0.0], [mu1], mass=m, h=h, g=g, v_k=v, mu2=np.array([mu2]))
+        ref = oracle.vfpi(p, max_iters=200, tol=1e-15)
+        vg, lam, st, _ = gpu_step(p, max_iters=200, tol=1e-15)
+        assert np.abs(vg.ravel() - ref["v"]).max() <= 1e-14
+        v = vg.reshape(1, 3)
+        t = p.R[0] @ v[0]
+        angles.append(np.arctan2(t[2], t[1]))
+    turn = abs(angles[-1] - angles[0])
+    say(f"  sliding particle: tangent-frame velocity angle turned by {turn:.3f} rad over 30 steps")
+    assert turn > 0.05
+
+
+def test_aniso_unsupported_combinations():
+    p = _aniso(scenes.random_problem(100, 20, 1), 5)
+    s = solver_for(p)
+    A, Jc, b, v = upload(p)
+    with pytest.raises(vf.VfpiError, match="not supported"):
+        s.step(A, b, Jc, v, projection="proximal")
+    tape = s.tape(p.n_nodes, p.n_contacts)
+    s.step(A, b, Jc, v, max_iters=50, tape=tape)
+    with pytest.raises(vf.VfpiError, match="not supported"):
+        s.step_backward(A, Jc, tape, torch.zeros(p.n, dtype=torch.float64, device="cuda"))
+    bad = p.mu2.copy()
+    bad[3] = -0.1
+    Jc.mu2 = torch.as_tensor(bad, device="cuda")
+    _, st = s.step(A, b, Jc, v, max_iters=5)
+    assert vf.read_stats(st)[0]["status"] & _abi.VFPI_S_BAD_MU

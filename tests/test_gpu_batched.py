@@ -29,7 +29,7 @@ def _upload_batch(batch, dev):
     p = batch.problem
     A = vf.bsr_from_arrays(p.n_nodes, p.row_ptr, p.col_idx, p.val, dtype=torch.float32, device=dev)
     crp, ccol, cval = p.jc_bsr()
-    Jc = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, dtype=torch.float32, device=dev)
+    Jc = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, dtype=torch.float32, device=dev, mu2=p.mu2)
     b = torch.as_tensor(p.b, device=dev).float()
     v = torch.as_tensor(p.v0, device=dev).float()
     no = torch.as_tensor(batch.env_node_off, device=dev)
