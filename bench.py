@@ -41,6 +41,14 @@ def sweep_bytes(n_nodes, nnzb, n_contacts, w):
             + n_contacts * (12 * w + 3 * w))
 
 
+def kernel_name(variant):
+    """The persistent sweep kernel a vfpi_step variant runs."""
+    kind = variant & 0xff
+    return {1: "k_vfpi_grid<1,NW> (lane per node, grid)", 2: "k_vfpi_grid<3,NW> (lane per row, grid)",
+            3: "k_vfpi_grid<1,NW> (one workgroup)", 4: "k_vfpi_grid<3,5> (one workgroup)",
+            5: "k_vfpi_regs (A's first levels in registers, grid)"}.get(kind, f"kind {kind}")
+
+
 def kernel_sources_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2201_09212_amd", "csrc")
@@ -121,7 +129,7 @@ def plain_bench(args, torch, vf, scenes):
         "variant": variant,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_vfpi_grid (persistent sweep loop)",
+                     "kernel": kernel_name(variant),
                      "bytes_per_launch": per_sweep * L},
     }
 
@@ -236,6 +244,13 @@ def adjoint_bench(args, torch, vf, scenes):
     kk = torch.tensor(1e3, device=dev, dtype=torch.float64, requires_grad=True)
     mu = torch.full((sc.n_nodes,), 0.5, device=dev, dtype=torch.float64, requires_grad=True)
     steps = args.rollout_steps
+    # warm-up of both paths (first-call costs of the assembly ops and autograd)
+    with torch.no_grad():
+        rollout(tc, s, x0t, v0t, (kk, mu), 10)
+    xw, _ = rollout(tc, s, x0t, v0t, (kk, mu), 10, checkpoint_every=10)
+    ((xw - target) ** 2).sum().backward()
+    kk.grad = None
+    mu.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.no_grad():

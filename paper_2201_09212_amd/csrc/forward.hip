@@ -336,11 +336,20 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
 // v^{l+1} through LDS so every wave stores whole cache lines; lambda and the
 // tape are written once, after the last sweep.  Same arithmetic and order as
 // the streaming kernel.
-template <int NW, int KC, bool COH>
+template <int NW, int KC, bool COH, bool CH>
 __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
+  // Registers hold what every sweep streams through the FMA chains: A's first
+  // KC levels, the gathered neighbour values and the node's own iterate.  The
+  // per-node constants (b, W, the contact record) and the last sweep's contact
+  // results live in LDS, which keeps the kernel within the 256 architectural
+  // VGPRs (beyond them the compiler parks A in AGPRs and copies it back every
+  // sweep).  CH: Chebyshev acceleration (keeps v^{l-1} in registers).
   __shared__ double s_red[NW];
   __shared__ int s_ired[3 * NW];
   __shared__ double s_out[NW][192];
+  __shared__ double s_bw[NW][6][64];      // b (3), W (3)
+  __shared__ double s_cr[NW][kPack][64];  // contact record of the lane's node
+  __shared__ double s_lam[NW][6][64];     // lambda, lambda* of the last sweep
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
   const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -385,31 +394,32 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     off += ck;
   }
   const int64_t off_tail = off;
-  double bi[3] = {0.0, 0.0, 0.0}, wi[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
+  double vo[3] = {0.0, 0.0, 0.0};
   int m = -1;
-  ContactRec<double> cr{};
   if (act) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      bi[r] = d.b[3 * i + r];
-      wi[r] = d.w[3 * i + r];
+      s_bw[slot][r][lane] = d.b[3 * i + r];
+      s_bw[slot][3 + r][lane] = d.w[3 * i + r];
       vo[r] = a.v_user[3 * i + r];
     }
     m = d.cmap[i];
-    if (m >= 0) cr = load_contact<double>(d.cpack + kPack * (int64_t)m);
+    if (m >= 0)
+      for (int e = 0; e < kPack; ++e) s_cr[slot][e][lane] = d.cpack[kPack * (int64_t)m + e];
   }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) s_lam[slot][e][lane] = 0.0;
   const bool isd = m >= 0 && is_dcontact(d, m);
   const bool owner = !isd || d.cpair[2 * (int64_t)m] == i;  // reports lambda
-  double lam[3] = {0.0, 0.0, 0.0}, ls[3] = {0.0, 0.0, 0.0};
-  double vp[3] = {vo[0], vo[1], vo[2]};  // v^{l-1} for Chebyshev acceleration (v^0 = v^1)
+  double vp[3] = {vo[0], vo[1], vo[2]};  // v^{l-1} (Chebyshev only; v^0 = v^1)
   int br = BR_OPEN;
   double* vcur = a.v_user;
   double* vnext = a.v_alt;
   Cheby ch;
-  ch.ls = a.cheby_ls;
+  ch.ls = CH ? a.cheby_ls : 0;
   ch.u = a.cheby_u;
   for (int l = 1;; ++l) {
-    const double nu = ch.next_nu(l);
+    const double nu = CH ? ch.next_nu(l) : 1.0;
     double xs[KC][3];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -429,27 +439,43 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
       }
     }
-    spmv_rows3_from<double, COH, (NW >= 8 ? 2 : 4)>(d.scol, d.sval, vcur, base, nk, lane, KC, off_tail, Av);
+    spmv_rows3_from<double, COH, (NW >= 8 ? 2 : 1)>(d.scol, d.sval, vcur, base, nk, lane, KC, off_tail, Av);
     double th2 = 0.0;
     double vn[3] = {0.0, 0.0, 0.0};
     if (act) {
       double vs[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        vs[r] = vo[r] - wi[r] * (Av[r] - bi[r]);
+        vs[r] = vo[r] - s_bw[slot][3 + r][lane] * (Av[r] - s_bw[slot][r][lane]);
         vn[r] = vs[r];
       }
       if (isd) {
+        double lam[3], ls[3];
         (void)dcontact_node<double, COH>(d, vcur, d.w, 0.0, 0.0, i, m, vs, vn, lam, ls, br);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          s_lam[slot][r][lane] = lam[r];
+          s_lam[slot][3 + r][lane] = ls[r];
+        }
       } else if (m >= 0) {
+        ContactRec<double> cr;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) cr.R[e] = s_cr[slot][e][lane];
+        cr.phi = s_cr[slot][9][lane];
+        cr.mu = s_cr[slot][10][lane];
+        cr.g = s_cr[slot][11][lane];
+        cr.mu2 = s_cr[slot][12][lane];
+        double lam[3], ls[3];
         br = contact_solve<double>(cr, vs[0], vs[1], vs[2], d.proj, lam, ls);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
-          vn[r] = vs[r] + wi[r] * F;
+          vn[r] = vs[r] + s_bw[slot][3 + r][lane] * F;
+          s_lam[slot][r][lane] = lam[r];
+          s_lam[slot][3 + r][lane] = ls[r];
         }
       }
-      if (ch.ls) {
+      if (CH && ch.ls) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const double p = vp[r];
@@ -481,14 +507,14 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     vcur = vnext;
     vnext = t;
     if (stop) break;
-    ch.observe(theta);
+    if (CH) ch.observe(theta);
   }
   int cb[3] = {0, 0, 0};
   if (act && m >= 0 && owner) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      d.lambda[3 * (int64_t)m + r] = lam[r];
-      if (d.tape_lamstar) d.tape_lamstar[3 * (int64_t)m + r] = ls[r];
+      d.lambda[3 * (int64_t)m + r] = s_lam[slot][r][lane];
+      if (d.tape_lamstar) d.tape_lamstar[3 * (int64_t)m + r] = s_lam[slot][3 + r][lane];
     }
     if (d.tape_branch) d.tape_branch[m] = br;
     cb[br] = 1;
@@ -571,12 +597,16 @@ hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
   if (g > cap) return hipErrorInvalidValue;
   GridArgs arg = ga;
   void* params[] = {&arg};
+  const bool ch = ga.cheby_ls > 0;
   if (g == 1) {  // one workgroup: plain loads, no cooperative launch needed
-    hipLaunchKernelGGL((k_vfpi_regs<NW, KC, false>), dim3(1), dim3(64 * NW), 0, st, ga);
+    if (ch)
+      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, false, true>), dim3(1), dim3(64 * NW), 0, st, ga);
+    else
+      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, false, false>), dim3(1), dim3(64 * NW), 0, st, ga);
     return hipGetLastError();
   }
-  return hipLaunchCooperativeKernel((const void*)k_vfpi_regs<NW, KC, true>, dim3((unsigned)g), dim3(64 * NW), params,
-                                    0, st);
+  const void* kern = ch ? (const void*)k_vfpi_regs<NW, KC, true, true> : (const void*)k_vfpi_regs<NW, KC, true, false>;
+  return hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * NW), params, 0, st);
 }
 
 // Barzilai-Borwein step sizes: the two-phase kernel, grid (kind 1) or one

@@ -143,6 +143,7 @@ struct Cheby {
   double nu = 1.0, rho = 0.0, theta_prev = 0.0;
   // nu_{l+1} used by sweep l
   VFPI_DEV double next_nu(int l) {
+    if (ls == 0) return nu = 1.0;  // off: plain V-FPI, no divisions
     if (l < ls) nu = 1.0;
     else if (l == ls) nu = 2.0 / (2.0 - rho * rho);
     else nu = 4.0 / (4.0 - rho * rho * nu);
