@@ -71,9 +71,10 @@ def load_traffic(name, per_launch_units):
     return t.get("bytes_per_launch")
 
 
-def plain_bench(args, torch, vf, scenes):
-    sc, x, v = scenes.cloth_cfg2(args.seed)
-    p = sc.assemble(x, v)
+def plain_bench(args, torch, vf, scenes, p=None, variant=None, traffic_name="cloth128"):
+    if p is None:
+        sc, x, v = scenes.cloth_cfg2(args.seed)
+        p = sc.assemble(x, v)
     dev = torch.device("cuda", 0)
     A = vf.bsr_from_arrays(p.n_nodes, p.row_ptr, p.col_idx, p.val, device=dev)
     crp, ccol, cval = p.jc_bsr()
@@ -84,7 +85,7 @@ def plain_bench(args, torch, vf, scenes):
     stats = vf.new_stats(1, dev)
     s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
     L = args.sweeps
-    variant = args.variant
+    variant = args.variant if variant is None else variant
     if variant == 0:
         from paper_2201_09212_amd import autotune
         variant = autotune.best_step_variant(s, A, b, Jc, vv, lam, stats)
@@ -117,7 +118,7 @@ def plain_bench(args, torch, vf, scenes):
     setup_avg = sum(setup_ms) / len(setup_ms)
     per_sweep = sweep_bytes(p.n_nodes, p.nnzb, p.n_contacts, 8)
     achieved = per_sweep * L / (solve_avg * 1e-3) / 1e9
-    traffic = load_traffic("cloth128", L)
+    traffic = load_traffic(traffic_name, L) if traffic_name else None
     return p, {
         "ms_per_step": ms_total / args.steps,
         "wall_s": wall,
@@ -297,6 +298,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-soft", action="store_true", help="skip the FEM and 10x10 cloth legs")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-variant", type=int, default=0)
     ap.add_argument("--rollout-steps", type=int, default=100)
@@ -325,6 +327,19 @@ def main():
         "dof_iters_per_s": p.n * args.sweeps * args.steps / (r["ms_per_step"] * args.steps * 1e-3),
         "roofline": r["roofline"],
     }
+    if not args.no_soft:
+        # the other single-instance workloads: the FEM soft block and the 10x10 cloth
+        for key, make, var in (("fem", lambda: scenes.fem_cfg3(args.seed), 5 | (8 << 8)),
+                               ("cloth10", lambda: scenes.cloth_cfg1(args.seed), 5 | (2 << 8))):
+            sc_, x_, v_ = make()
+            q = sc_.assemble(x_, v_)
+            _, rq = plain_bench(args, torch, vf, scenes, p=q, variant=var, traffic_name=None)
+            out[key] = {"workload": {"fem": "FEM block 64x64x16 cells, 5 tets/cell, FP64",
+                                     "cloth10": "10x10 cloth landing on a plane, FP64"}[key],
+                        "n_nodes": q.n_nodes, "nnzb": q.nnzb, "n_contacts": q.n_contacts,
+                        "contact_iters_per_s": rq["value"], "sweep_us": rq["sweep_us"], "variant": var,
+                        "hbm_gbps": rq["roofline"]["achieved"], "hbm_frac": rq["roofline"]["frac"],
+                        "kernel": rq["roofline"]["kernel"]}
     if not args.no_batched:
         out["batched"] = batched_bench(args, torch, vf, scenes)
     if not args.no_adjoint:

@@ -330,6 +330,198 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
   });
 }
 
+// Register-resident adjoint (S-contacts; one pass: every workgroup owns at
+// most NW chunks).  A lane keeps its node's first KC block levels of A and
+// its own g~, t and u in registers for the whole solve; only s = W t goes
+// through memory, written as whole lines through LDS and gathered coherently
+// by the neighbours' products.  Same sweeps and arithmetic order as k_adjoint.
+template <int NW, int KC>
+__global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
+  __shared__ double s_red[NW];
+  __shared__ double s_out[NW][192];
+  const int G = gridDim.x;
+  const int lb = xcd_logical_block(blockIdx.x, G);
+  const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nch = (a.n_nodes + 63) / 64;
+  const int64_t c0 = lb * nch / G, c1 = (lb + 1) * nch / G;
+  const int64_t c = c0 + slot;
+  const int64_t n0 = c * 64;
+  const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
+  const int64_t i = n0 + lane;
+  const bool act = lane < cnt;
+  const int flags = *a.flags;
+  if (flags != 0) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_nodes; k += (int64_t)G * blockDim.x)
+      a.grad_b[k] = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.n_contacts; k += (int64_t)G * blockDim.x)
+      a.grad_phi[k] = a.grad_mu[k] = 0.0;
+    if (a.grad_A)
+      for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 9 * (int64_t)a.nnzb;
+           k += (int64_t)G * blockDim.x)
+        a.grad_A[k] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.stats->iters = 0;
+      a.stats->status = flags;
+      a.stats->theta = INFINITY;
+      a.stats->n_open = a.stats->n_stick = a.stats->n_slip = a.stats->reserved = 0;
+    }
+    return;
+  }
+  const int nk = act ? a.row_ptr[i + 1] - a.row_ptr[i] : 0;
+  const int64_t base = cnt > 0 ? a.row_ptr[n0] : 0;
+  int col[KC];
+  double av[KC][9];
+  int64_t off = 0;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const uint64_t mk = ballot(k < nk);
+    const int ck = __popcll(mk);
+    col[k] = 0;
+    if (k < nk) {
+      const int pos = lanes_below(mk, lane);
+      const int64_t q = base + off;
+      col[k] = a.scol[q + pos];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) av[k][e] = a.sval[9 * q + (int64_t)e * ck + pos];
+    }
+    off += ck;
+  }
+  const int64_t off_tail = off;
+  const int m = act ? a.cmap[i] : -1;
+  double w3[3] = {0.0, 0.0, 0.0};
+  if (act)
+    for (int r = 0; r < 3; ++r) w3[r] = a.w[3 * i + r];
+  // y = A x for this lane's row (every thread calls)
+  auto spmv = [&](const double* x, double out[3]) {
+    double xs[KC][3];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      if (k < nk) {
+        const double* xp = x + 3 * (int64_t)col[k];
+        xs[k][0] = ldv<true>(xp);
+        xs[k][1] = ldv<true>(xp + 1);
+        xs[k][2] = ldv<true>(xp + 2);
+      }
+    }
+    out[0] = out[1] = out[2] = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      if (k < nk) {
+        out[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
+        out[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
+        out[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
+      }
+    }
+    spmv_rows3_from<double, true, (NW >= 8 ? 2 : 1)>(a.scol, a.sval, x, base, nk, lane, KC, off_tail, out);
+  };
+  // store this wave's node values as whole lines (every thread calls)
+  auto publish = [&](double* dst, const double x[3]) {
+    if (act)
+      for (int r = 0; r < 3; ++r) s_out[slot][3 * lane + r] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int e = lane + 64 * j;
+      if (e < 3 * cnt) stv<true>(dst + 3 * n0 + e, s_out[slot][e]);
+    }
+  };
+  int seq = 0;
+  // phase A: e = J^T Gamma^-1 D_P^T g_lam, p = W e
+  double e3[3] = {0.0, 0.0, 0.0};
+  if (a.gl) {
+    if (m >= 0) {
+      const double* R = a.cpack + kPack * (int64_t)m;
+      double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
+      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+      const double gi = 1.0 / R[11];
+      for (int r = 0; r < 3; ++r) e3[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
+    }
+    const double p3[3] = {w3[0] * e3[0], w3[1] * e3[1], w3[2] * e3[2]};
+    publish(a.S[1], p3);
+    grid_barrier(a.slots, G, lb, ++seq, s_red);
+  }
+  // phase B: g~ = g_v - e + A p; u0 = g~, t0 = G^T u0, s0 = W t0
+  double gt[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0}, tt[3] = {0.0, 0.0, 0.0};
+  {
+    double Ap[3] = {0.0, 0.0, 0.0};
+    if (a.gl) spmv(a.S[1], Ap);
+    if (act) {
+      for (int r = 0; r < 3; ++r) gt[r] = a.gl ? a.gv[3 * i + r] - e3[r] + Ap[r] : a.gv[3 * i + r];
+      gt_node(a, i, m, gt, tt);
+      for (int r = 0; r < 3; ++r) uu[r] = gt[r];
+    }
+    const double s3[3] = {w3[0] * tt[0], w3[1] * tt[1], w3[2] * tt[2]};
+    publish(a.S[0], s3);
+    grid_barrier(a.slots, G, lb, ++seq, s_red);
+  }
+  int cur = 0;
+  if (a.max_iters > 0) {
+    for (int l = 1;; ++l) {
+      const int nxt = cur ^ 1;
+      double As[3];
+      spmv(a.S[cur], As);
+      double th2 = 0.0;
+      if (act) {
+        double un[3], tn[3];
+        for (int r = 0; r < 3; ++r) un[r] = gt[r] + tt[r] - As[r];
+        gt_node(a, i, m, un, tn);
+        for (int r = 0; r < 3; ++r) {
+          const double d = un[r] - uu[r];
+          th2 += d * d;
+          uu[r] = un[r];
+          tt[r] = tn[r];
+        }
+      }
+      const double s3[3] = {w3[0] * tt[0], w3[1] * tt[1], w3[2] * tt[2]};
+      publish(a.S[nxt], s3);
+      th2 = block_sum(th2, s_red);
+      const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+      cur = nxt;
+      if (stop) break;
+    }
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.stats->iters = 0;
+    a.stats->status = VFPI_S_MAXITER;
+    a.stats->theta = INFINITY;
+    a.stats->n_open = a.stats->n_stick = a.stats->n_slip = a.stats->reserved = 0;
+  }
+  // final gradients (A_bar reads the solution v of the neighbours from the tape)
+  if (!act) return;
+  double q[3] = {uu[0], uu[1], uu[2]};
+  if (m >= 0) {
+    const double* R = a.cpack + kPack * (int64_t)m;
+    const double wb = w3[0];
+    double rr[3], y[3], dmu;
+    for (int k = 0; k < 3; ++k) {
+      rr[k] = R[3 * k] * (wb * uu[0]) + R[3 * k + 1] * (wb * uu[1]) + R[3 * k + 2] * (wb * uu[2]);
+      if (a.gl) rr[k] += a.gl[3 * (int64_t)m + k];
+    }
+    dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], rr, y, &dmu);
+    const double gi = 1.0 / R[11];
+    for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
+    a.grad_phi[m] = -y[0] * gi;
+    a.grad_mu[m] = dmu;
+  }
+  double bb[3];
+  for (int r = 0; r < 3; ++r) {
+    bb[r] = w3[r] * q[r];
+    a.grad_b[3 * i + r] = bb[r];
+  }
+  if (a.grad_A) {
+    const int64_t rp = a.row_ptr[i], re = a.row_ptr[i + 1];
+    for (int64_t k = rp; k < re; ++k) {
+      const int64_t cc = a.col_idx[k];
+      const double v0 = a.vsol[3 * cc], v1 = a.vsol[3 * cc + 1], v2 = a.vsol[3 * cc + 2];
+      double* g = a.grad_A + 9 * k;
+      for (int r = 0; r < 3; ++r) {
+        g[3 * r] = -bb[r] * v0;
+        g[3 * r + 1] = -bb[r] * v1;
+        g[3 * r + 2] = -bb[r] * v2;
+      }
+    }
+  }
+}
+
 }  // namespace vfpi
 
 using namespace vfpi;
@@ -425,6 +617,26 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
 
   const int kind = opts->variant & 0xff;
   const int grid_req = (opts->variant >> 16) & 0xff;
+  // register-resident adjoint: S-contacts, variant 0 or kind 5, one workgroup
+  // per CU at most with the fewest chunk slots that fit
+  if (!aa.cpair && (kind == 0 || kind == 5)) {
+    const int64_t cap = ctx->num_cu < kMaxGridSlots ? ctx->num_cu : kMaxGridSlots;
+    int want_nw = (opts->variant >> 8) & 0xff;
+    for (int nw : {2, 4, 8}) {
+      if (want_nw && nw < want_nw) continue;
+      int64_t g = (nch + nw - 1) / nw;
+      if (g > 8 && g % 8 != 0) g += 8 - g % 8;
+      if (g > nch) g = nch;
+      if (g > cap) continue;
+      void* params[] = {&aa};
+      const void* kern = nw == 2 ? (const void*)k_adjoint_regs<2, 9>
+                         : nw == 4 ? (const void*)k_adjoint_regs<4, 9> : (const void*)k_adjoint_regs<8, 4>;
+      vfpi_mark(ctx, 1, stream);
+      VFPI_CHECK_HIP(hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * nw), params, 0, stream));
+      vfpi_mark(ctx, 2, stream);
+      return VFPI_OK;
+    }
+  }
   constexpr int NW = 4;
   auto kern = k_adjoint<NW>;
   const int threads = 64 * NW;

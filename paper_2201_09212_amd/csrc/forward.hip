@@ -542,13 +542,35 @@ struct Variant {
   int grid;   // workgroup cap (0 = one per CU)
 };
 
-Variant decode_variant(int32_t v, int32_t n_nodes) {
+// Library default (variant 0): the register-resident kernel with the fewest
+// chunk slots per workgroup that still fits one workgroup per CU; the
+// streaming kernels when the problem is larger (or for BB step sizes, which
+// have their own kernel in kinds 1 and 3).
+Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu, bool bb) {
   Variant x;
   x.kind = v & 0xff;
   x.nw = (v >> 8) & 0xff;
   x.grid = (v >> 16) & 0xff;
-  if (x.kind == 0) x.kind = (n_nodes <= 1024) ? 3 : 1;
-  if (x.nw == 0) x.nw = (x.kind == 3) ? 16 : (x.kind == 4 ? 5 : (x.kind == 1 ? 2 : 1));
+  if (x.kind == 0) {
+    const int64_t nch = ((int64_t)n_nodes + 63) / 64;
+    const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
+    if (bb) {
+      x.kind = (n_nodes <= 1024) ? 3 : 1;
+    } else {
+      x.kind = 1;
+      for (int nw : {2, 4, 8}) {
+        int64_t g = (nch + nw - 1) / nw;
+        if (g > 8 && g % 8 != 0) g += 8 - g % 8;
+        if (g > nch) g = nch;
+        if (g <= cap) {
+          x.kind = 5;
+          if (x.nw == 0) x.nw = nw;
+          break;
+        }
+      }
+    }
+  }
+  if (x.nw == 0) x.nw = (x.kind == 3) ? 16 : (x.kind == 4 ? 5 : (x.kind == 1 ? 2 : (x.kind == 5 ? 2 : 1)));
   return x;
 }
 
@@ -739,7 +761,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.amax = reinterpret_cast<const unsigned long long*>(ctx->sync + SY_AMAX);
   ga.tape_w = tv.w;
 
-  Variant vr = decode_variant(opts->variant, N);
+  Variant vr = decode_variant(opts->variant, N, ctx->num_cu, bb);
   if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
   vfpi_mark(ctx, 1, stream);
   hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream) : launch_variant(vr, ga, ctx->num_cu, N, stream);

@@ -39,13 +39,14 @@ def _cases():
         yield f"random{n}", scenes.random_problem(n, nc, seed, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("with_glam", [False, True])
 @pytest.mark.parametrize("name,p", list(_cases()))
-def test_adjoint_matches_oracle(name, p, with_glam):
+def test_adjoint_matches_oracle(name, p, with_glam, variant):
     g = np.random.default_rng(3)
     gv = g.normal(size=p.n)
     gl = g.normal(size=3 * p.n_contacts) if with_glam else None
-    out = gpu_fwd_bwd(p, gv, gl)
+    out = gpu_fwd_bwd(p, gv, gl, variant=variant)
     fwd = oracle.vfpi(p, max_iters=200000, tol=1e-14)
     ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
     assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
@@ -90,14 +91,19 @@ def test_adjoint_vs_central_differences_of_gpu_forward():
 
 
 def test_adjoint_grid_and_single_workgroup_agree():
+    """The register-resident adjoint (default; kind 5 with 2 or 8 chunk
+    slots), the streaming one (kind 1) and one workgroup (kind 3) agree."""
     sc, x, v = scenes.cloth_cfg5_scene(0)
     x[:, 2] = np.random.default_rng(1).uniform(-5e-4, 4e-3, size=x.shape[0])
     p = sc.assemble(x, v)
     gv = np.random.default_rng(2).normal(size=p.n)
     a = gpu_fwd_bwd(p, gv, tol=1e-13)
-    b = gpu_fwd_bwd(p, gv, tol=1e-13, variant=3)
-    for k in ("b", "phi", "mu"):
-        assert rel(a[k], b[k]) <= 1e-10
+    for var in (1, 3, 5 | (8 << 8)):
+        b = gpu_fwd_bwd(p, gv, tol=1e-13, variant=var)
+        say(f"  adjoint variant {var:#x}: {b['bwd_stats']['iters']} sweeps (default {a['bwd_stats']['iters']})")
+        assert abs(b["bwd_stats"]["iters"] - a["bwd_stats"]["iters"]) <= 1
+        for k in ("b", "A", "phi", "mu"):
+            assert rel(a[k], b[k]) <= 1e-10, (var, k)
     fwd = oracle.vfpi(p, max_iters=200000, tol=1e-13)
     ref = oracle_adjoint(p, fwd, gv, tol=1e-14)
     errs = {k: rel(a[k], ref[k]) for k in ("b", "A", "phi", "mu")}
