@@ -192,7 +192,9 @@ int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_cont
  * env_con_off[e+1]); A, b, Jc, v, lambda use global node/contact indices and
  * FP32 values.  env_order (device [n_env] permutation, or NULL) is the order
  * in which the persistent kernel's work queue hands out envs (largest first is
- * a good choice).  per_env_stats: device [n_env].  Every option applies to
+ * a good choice).  Launch kinds (opts.variant): 1 lane per node, 2 lane per
+ * row, 3 lane per node with two workgroups per CU.  per_env_stats: device
+ * [n_env].  Every option applies to
  * every env; each env stops on its own theta.  W modes: FROBENIUS,
  * USER_SCALAR.  Errors as vfpi_step. */
 int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* env_node_off,

@@ -57,8 +57,10 @@ struct BatchArgs {
 
 __global__ void k_reset_queue(uint32_t* q) { *q = 0u; }
 
-template <int TPN, int NW>
-__global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_batched(BatchArgs a) {
+// MW: minimum waves per SIMD the registers must allow (4 lets two 8-wave
+// workgroups share a CU, so two environments are in flight per CU).
+template <int TPN, int NW, int MW = 1>
+__global__ void __launch_bounds__(64 * TPN * NW, MW) k_vfpi_batched(BatchArgs a) {
   __shared__ float s_vs[2][TPN == 3 ? NW : 1][3][64];
   __shared__ double s_red[TPN * NW];
   __shared__ int s_ired[3 * TPN * NW];
@@ -211,9 +213,9 @@ using namespace vfpi;
 
 namespace {
 
-template <int TPN, int NW>
+template <int TPN, int NW, int MW = 1>
 hipError_t launch_batched(const BatchArgs& ba, int grid_req, int num_cu, hipStream_t st) {
-  auto kern = k_vfpi_batched<TPN, NW>;
+  auto kern = k_vfpi_batched<TPN, NW, MW>;
   const int threads = 64 * TPN * NW;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
@@ -304,6 +306,9 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   if (kind == 2) {
     e = (nw >= 2) ? launch_batched<3, 2>(ba, grid, ctx->num_cu, stream)
                   : launch_batched<3, 1>(ba, grid, ctx->num_cu, stream);
+  } else if (kind == 3) {  // lane per node, two workgroups per CU
+    e = (nw >= 8) ? launch_batched<1, 8, 4>(ba, grid, ctx->num_cu, stream)
+                  : launch_batched<1, 4, 4>(ba, grid, ctx->num_cu, stream);
   } else if (kind == 0 || kind == 1) {
     e = (nw >= 8)   ? launch_batched<1, 8>(ba, grid, ctx->num_cu, stream)
         : (nw >= 4) ? launch_batched<1, 4>(ba, grid, ctx->num_cu, stream)

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 VARIANTS = {"node1": 1 | (1 << 8), "node2": 1 | (2 << 8), "node4": 1 | (4 << 8), "node8": 1 | (8 << 8),
-            "row1": 2 | (1 << 8), "row2": 2 | (2 << 8), "node4_3wg": 1 | (4 << 8) | (3 << 16)}
+            "row1": 2 | (1 << 8), "row2": 2 | (2 << 8), "node4_3wg": 1 | (4 << 8) | (3 << 16),
+            "node4_occ4": 3 | (4 << 8), "node8_occ4": 3 | (8 << 8)}
 
 
 def _envs_small():
@@ -112,11 +113,12 @@ def test_batched_bad_env_isolated():
     _check_envs(batch, v, lam, st, 10, envs_idx=good)
 
 
-def test_full_batch_sampled():
+@pytest.mark.parametrize("variant", [0, 3 | (8 << 8)])
+def test_full_batch_sampled(variant):
     envs = [sc.assemble(x, v) for sc, x, v in scenes.cloth_cfg4_envs(0)]
     batch = scenes.concat_problems(envs)
     L = 25
-    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True)
+    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True, variant=variant)
     sample = np.random.default_rng(0).choice(batch.n_env, 40, replace=False)
     sizes = [envs[e].n_nodes for e in sample]
     worst = _check_envs(batch, v, lam, st, L, envs_idx=sample)
