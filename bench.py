@@ -329,7 +329,7 @@ def main():
     }
     if not args.no_soft:
         # the other single-instance workloads: the FEM soft block and the 10x10 cloth
-        for key, make, var in (("fem", lambda: scenes.fem_cfg3(args.seed), 5 | (8 << 8)),
+        for key, make, var in (("fem", lambda: scenes.fem_cfg3(args.seed), 5 | (5 << 8)),
                                ("cloth10", lambda: scenes.cloth_cfg1(args.seed), 5 | (2 << 8))):
             sc_, x_, v_ = make()
             q = sc_.assemble(x_, v_)

@@ -558,7 +558,7 @@ Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu, bool bb) {
       x.kind = (n_nodes <= 1024) ? 3 : 1;
     } else {
       x.kind = 1;
-      for (int nw : {2, 4, 8}) {
+      for (int nw : {2, 4, 5, 6, 8}) {
         int64_t g = (nch + nw - 1) / nw;
         if (g > 8 && g % 8 != 0) g += 8 - g % 8;
         if (g > nch) g = nch;
@@ -653,6 +653,8 @@ hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int
       return (vr.nw <= 1)   ? launch_regs<1, 9>(ga, vr.grid, num_cu, N, stream)
              : (vr.nw <= 2) ? launch_regs<2, 9>(ga, vr.grid, num_cu, N, stream)
              : (vr.nw <= 4) ? launch_regs<4, 9>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 5) ? launch_regs<5, 4>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 6) ? launch_regs<6, 4>(ga, vr.grid, num_cu, N, stream)
                             : launch_regs<8, 4>(ga, vr.grid, num_cu, N, stream);
     case 1:
       return (vr.nw <= 1)   ? launch_grid<1, 1>(ga, vr.grid, num_cu, N, false, stream)

@@ -30,6 +30,8 @@ VARIANTS = {
     "regs_node1": 5 | (1 << 8),
     "regs_node2": 5 | (2 << 8),
     "regs_node4": 5 | (4 << 8),
+    "regs_node5": 5 | (5 << 8),
+    "regs_node6": 5 | (6 << 8),
     "regs_node8": 5 | (8 << 8),
     "regs_node1_grid16": 5 | (1 << 8) | (16 << 16),
 }
@@ -100,7 +102,7 @@ def test_cloth128_full_size():
 def test_fem_full_size():
     sc, x, v = scenes.fem_cfg3(0)
     p = sc.assemble(x, v)
-    for variant in (0, 1 | (4 << 8), 2, 1 | (2 << 8), 5 | (8 << 8)):
+    for variant in (0, 1 | (4 << 8), 2, 1 | (2 << 8), 5 | (5 << 8), 5 | (6 << 8), 5 | (8 << 8)):
         _compare(p, 20, variant)
 
 
