@@ -132,8 +132,15 @@ typedef struct {
   double  alpha_user;    /* VFPI_W_USER_SCALAR only                             */
   int32_t reuse_w;       /* 1: keep the row sums a_dd, ||A_d*||^2 of the previous
                             call on this context (W reuse across steps, Sec. IV-C) */
-  int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16;
-                            0 = library default (see paper_2201_09212_amd/autotune.py) */
+  int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16.
+                            vfpi_step kinds: 1 grid, lane per node; 2 grid, lane per row;
+                            3, 4 the same in one workgroup; 5 grid, the node's first
+                            block levels of A in registers (refused with VFPI_E_OPTS when
+                            it needs more than one workgroup per CU).  0 = library
+                            default: kind 5 with the fewest chunk slots (2, 4, 5, 6, 8)
+                            that fit, else kind 1 (BB: kind 3 up to 1024 nodes, else 1).
+                            vfpi_step_backward: 0 or 5 register-resident (S-contacts),
+                            1 streaming, 3 one workgroup.  Batched kinds: see below. */
   int32_t cheby_ls;      /* 0: off; l_s >= 1: Chebyshev acceleration (Alg. 3):
                             nu = 1 before sweep l_s, 2/(2 - rho^2) at l_s, then
                             4/(4 - rho^2 nu); rho = min(theta_l / theta_{l-1}, 1) */
@@ -171,7 +178,7 @@ int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts);
 /* One plain FP64 V-FPI solve (Alg. 1 inner loop, Alg. 2 contact step).
  *   A       FP64 system matrix A_k (eq. lindyn)
  *   b       [n]  right-hand side b_k
- *   Jc      FP64 nodal contact Jacobian, phi, mu (S-contacts)
+ *   Jc      FP64 nodal contact Jacobian (S- and D-contacts), phi, mu, mu2
  *   v       [n]  in: warm start v^1 (Sec. V-A.5); out: v^{l+1} of the last sweep
  *   lambda  [3 n_c] out: contact impulses (n, t1, t2) of the last sweep
  *   opts    options (host struct)
@@ -180,7 +187,7 @@ int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts);
  *           receives what vfpi_step_backward needs
  * Errors: VFPI_E_NULL, VFPI_E_SHAPE (also Jc->nnzb > 2 n_c), VFPI_E_OPTS,
  * VFPI_E_CAPACITY, VFPI_E_UNSUPPORTED (BB modes with Chebyshev or with launch
- * kinds other than 1 and 3), VFPI_E_HIP. */
+ * kinds other than 1 and 3; mu2 with VFPI_PROJ_PROXIMAL), VFPI_E_HIP. */
 int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc,
               double* v, double* lambda, const vfpi_opts* opts, vfpi_stats* stats,
               void* tape, hipStream_t stream);
@@ -214,8 +221,9 @@ int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* env_node_off,
  *   opts      max_iters / tol of the adjoint's own fixed-point iteration
  * The adjoint u solves u = g + (I - A W) G^T u with G = I - W J^T D_P Gamma^-1 J
  * (D_P = projection Jacobian of the last sweep), by transposed sweeps that
- * reuse the forward's SpMV layout.  Errors as vfpi_step, plus VFPI_E_NO_TAPE
- * for tape == NULL. */
+ * reuse the forward's layout; D-contacts and opts.omega (which must equal
+ * the forward's) are supported.  Errors as vfpi_step, plus VFPI_E_NO_TAPE for
+ * tape == NULL and VFPI_E_UNSUPPORTED for VFPI_PROJ_PROXIMAL or mu2. */
 int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc,
                        const void* tape, const double* grad_v, const double* grad_lambda,
                        double* grad_b, double* grad_A_val, double* grad_phi, double* grad_mu,

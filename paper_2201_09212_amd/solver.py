@@ -53,7 +53,8 @@ class Bsr:
 
 @dataclasses.dataclass
 class Contacts:
-    """Nodal contact Jacobian rows (one SO(3) block per S-contact), phi, mu."""
+    """Nodal contact Jacobian rows ([R] for an S-contact, [R, -R] for a D-contact), phi,
+    mu and, for anisotropic friction, mu2."""
     n_contacts: int
     row_ptr: torch.Tensor
     col_idx: torch.Tensor
