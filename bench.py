@@ -9,9 +9,15 @@ resident in HBM.  Prints one JSON line:
   value        contact-iterations per second (sum of n_c * sweeps / solver time)
   roofline     the persistent sweep kernel: algorithmic bytes per launch over
                its average duration (HIP events on the launch stream)
-  cpu_baseline the CPU FP64 oracle on the same input, bounded sample
+  cpu_baseline the CPU FP64 oracle on the same input, bounded sample, one
+               core (cpu_baseline_multicore: one oracle process per core)
+  fem, cloth10 the FEM soft block and the 10x10 cloth, fixed sweeps
+  context      sweeps and time to theta < tol (plain and Chebyshev) on the
+               128x128 cloth and the paper-size FEM block
   batched      batched FP32 environments (env-steps/s), when enabled
   adjoint      backward/forward time ratio, when enabled
+  cpu_context  oracle V-FPI vs PGS (Delassus), the oracle adjoint step, and
+               the batched FP32 result's error on a sample of environments
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweeps L]
 """
@@ -71,10 +77,33 @@ def load_traffic(name, per_launch_units):
     return t.get("bytes_per_launch")
 
 
-def plain_bench(args, torch, vf, scenes, p=None, variant=None, traffic_name="cloth128"):
-    if p is None:
-        sc, x, v = scenes.cloth_cfg2(args.seed)
-        p = sc.assemble(x, v)
+def dist(xs):
+    """Mean, median and 90th percentile of a list of timings."""
+    s = sorted(xs)
+    return {"mean": sum(s) / len(s), "median": s[len(s) // 2], "p90": s[min(len(s) - 1, int(0.9 * len(s)))]}
+
+
+def copy_peak(torch, nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy rate (read + write bytes per second),
+    the practical HBM ceiling next to the 8 TB/s specification."""
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del x, y
+    return 2 * nbytes / (dist(ms)["median"] * 1e-3) / 1e9
+
+
+def upload(torch, vf, p):
+    """Device copies of one problem: A, b, J_c, v (warm start), lambda, stats."""
     dev = torch.device("cuda", 0)
     A = vf.bsr_from_arrays(p.n_nodes, p.row_ptr, p.col_idx, p.val, device=dev)
     crp, ccol, cval = p.jc_bsr()
@@ -82,7 +111,44 @@ def plain_bench(args, torch, vf, scenes, p=None, variant=None, traffic_name="clo
     b = torch.as_tensor(p.b, device=dev)
     vv = torch.as_tensor(p.v0, device=dev).clone()
     lam = torch.empty(3 * p.n_contacts, dtype=torch.float64, device=dev)
-    stats = vf.new_stats(1, dev)
+    return A, b, Jc, vv, lam, vf.new_stats(1, dev)
+
+
+def converge_runs(torch, vf, p, tols=(1e-4, 1e-6), cheby=(0, 10), reps=3, fixed=()):
+    """Iterations and solver time to reach theta < tol from the step's warm
+    start, plain and with Chebyshev acceleration (l_s = 10, u = 1), with the
+    library's default launch; optionally also fixed sweep counts."""
+    A, b, Jc, vv, lam, stats = upload(torch, vf, p)
+    v0 = vv.clone()
+    s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
+    runs = [dict(tol=t, cheby_ls=c) for c in cheby for t in tols] + [dict(fixed=L) for L in fixed]
+    out = []
+    vf.vfpi_timing_enable(s.ctx, True)
+    for r in runs:
+        if "fixed" in r:
+            opt = dict(max_iters=r["fixed"], fixed_iters=True)
+        else:
+            opt = dict(max_iters=100000, tol=r["tol"], cheby_ls=r["cheby_ls"])
+        ms, sms = [], []
+        for _ in range(reps + 1):
+            vv.copy_(v0)
+            s.step(A, b, Jc, vv, lam, stats=stats, **opt)
+            a_, c_ = vf.vfpi_timing_read(s.ctx)
+            sms.append(a_)
+            ms.append(c_)
+        st = vf.read_stats(stats)[0]
+        out.append({**r, "iters": st["iters"], "status": st["status"], "theta": st["theta"],
+                    "setup_ms": dist(sms[1:])["median"], "solve_ms": dist(ms[1:])["median"]})
+    vf.vfpi_timing_enable(s.ctx, False)
+    s.close()
+    return out
+
+
+def plain_bench(args, torch, vf, scenes, p=None, variant=None, traffic_name="cloth128"):
+    if p is None:
+        sc, x, v = scenes.cloth_cfg2(args.seed)
+        p = sc.assemble(x, v)
+    A, b, Jc, vv, lam, stats = upload(torch, vf, p)
     s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
     L = args.sweeps
     variant = args.variant if variant is None else variant
@@ -119,6 +185,7 @@ def plain_bench(args, torch, vf, scenes, p=None, variant=None, traffic_name="clo
     per_sweep = sweep_bytes(p.n_nodes, p.nnzb, p.n_contacts, 8)
     achieved = per_sweep * L / (solve_avg * 1e-3) / 1e9
     traffic = load_traffic(traffic_name, L) if traffic_name else None
+    sd = dist(solve_ms)
     return p, {
         "ms_per_step": ms_total / args.steps,
         "wall_s": wall,
@@ -126,12 +193,15 @@ def plain_bench(args, torch, vf, scenes, p=None, variant=None, traffic_name="clo
         "stats": st,
         "setup_ms": setup_avg,
         "solve_ms": solve_avg,
+        "solve_ms_median": sd["median"],
+        "solve_ms_p90": sd["p90"],
         "sweep_us": solve_avg * 1e3 / L,
         "variant": variant,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": kernel_name(variant),
-                     "bytes_per_launch": per_sweep * L},
+                     "bytes_per_launch": per_sweep * L,
+                     "dram_gbps": None if traffic is None else traffic / (solve_avg * 1e-3) / 1e9},
     }
 
 
@@ -191,6 +261,16 @@ def batched_bench(args, torch, vf, scenes):
     ms = e0.elapsed_time(e1) / args.steps
     st = vf.read_stats(stats)
     assert all(x["iters"] == L for x in st)
+    # one fresh step from the warm start, kept for the oracle comparison of a
+    # sample of environments (done in the CPU leg)
+    v.copy_(torch.as_tensor(p.v0, device=dev).float())
+    run()
+    torch.cuda.synchronize()
+    sizes = np.argsort([e.n_nodes for e in envs])
+    pick = sorted(set(int(sizes[k]) for k in np.linspace(0, len(envs) - 1, 16).astype(int)))
+    vh, lh = v.double().cpu().numpy(), lam.double().cpu().numpy()
+    sample = [(envs[e], vh[3 * batch.env_node_off[e]:3 * batch.env_node_off[e + 1]],
+               lh[3 * batch.env_con_off[e]:3 * batch.env_con_off[e + 1]]) for e in pick]
     s.close()
     kavg = sum(kms) / len(kms)
     per_sweep = sum(sweep_bytes(e.n_nodes, e.nnzb, e.n_contacts, 4) for e in envs)
@@ -198,6 +278,7 @@ def batched_bench(args, torch, vf, scenes):
     return {"value": batch.n_env / (ms * 1e-3), "unit": "env-step/s", "ms_per_step": ms, "n_env": batch.n_env,
             "n_nodes": p.n_nodes, "nnzb": p.nnzb, "n_contacts": p.n_contacts, "sweeps_per_step": L,
             "dtype": "f32 (f64 residual)", "graph": True, "variant": variant, "kernel_ms": kavg,
+            "kernel_ms_median": dist(kms)["median"], "kernel_ms_p90": dist(kms)["p90"], "_sample": sample,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBPS, "traffic": load_traffic("batched2048", L),
                          "kernel": "k_vfpi_batched (persistent, one launch per step)",
@@ -265,19 +346,77 @@ def adjoint_bench(args, torch, vf, scenes):
     t_fb = time.perf_counter() - t0
     s.close()
     fm, bm = sorted(fwd)[len(fwd) // 2], sorted(bwd)[len(bwd) // 2]
-    return {"step_fwd_ms": fm, "step_bwd_ms": bm, "bwd_over_fwd_step": bm / fm, "fwd_sweeps": fit,
+    return {"_cpu": (p, gv.cpu().numpy()),
+            "step_fwd_ms": fm, "step_bwd_ms": bm, "bwd_over_fwd_step": bm / fm, "fwd_sweeps": fit,
             "bwd_sweeps": bit, "n_contacts": p.n_contacts, "rollout_steps": steps,
             "rollout_fwd_s": t_fwd, "rollout_fwd_bwd_s": t_fb,
             "bwd_over_fwd_rollout": (t_fb - t_fwd) / t_fwd,
             "workload": "cloth64x64 on plane, FP64, converged to 1e-13, checkpoint every 10 steps"}
 
 
-def cpu_baseline(args, p, oracle_mod, budget_s):
+def context_bench(args, torch, vf, scenes):
+    """Convergence to theta < 1e-4 / 1e-6 (plain and Chebyshev) on the 128x128
+    cloth and on the paper-size FEM block (16x16x4 cells, 4,335 DOF), the
+    latter also at fixed 50 / 100 sweeps, next to the paper's soft-mat
+    timings (other scene and hardware: context only)."""
+    sc, x, v = scenes.fem_ctx(args.seed)
+    q = sc.assemble(x, v)
+    return {
+        "cloth128_converge": converge_runs(torch, vf, args._cloth128),
+        "fem16x16x4": {"n_nodes": q.n_nodes, "dof": q.n, "nnzb": q.nnzb, "n_contacts": q.n_contacts,
+                       "runs": converge_runs(torch, vf, q, tols=(1e-4, 1e-5, 1e-6), fixed=(50, 100)),
+                       "paper_context": "soft mat, 4438 DOF, i5-7500 4C CPU: 8.65 ms and 39.72 iterations at "
+                                        "1e-4 with Chebyshev; 10.85 / 20.90 ms at fixed 50 / 100 iterations"},
+    }
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline leg: the only part of the bench that runs the FP64 oracle
+# (on the host cores, bounded samples of the same inputs).
+
+_MC = {}
+
+
+def _oracle_worker(budget_s):
+    """Forked worker: the single-thread oracle on the parent's cloth input."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    p, L = _MC["p"], _MC["L"]
+    n = 0
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        while True:
+            oracle.vfpi(p, max_iters=L, fixed_iters=True)
+            n += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    return n
+
+
+def cpu_multicore(args, p, budget_s):
+    """The oracle on every host core at once (one forked process per core,
+    each a single-thread oracle on the same input): aggregate throughput.
+    Runs before the process touches the GPU."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    P = max(1, min(16, len(os.sched_getaffinity(0))))
+    _MC.update(p=p, L=args.sweeps)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(P, mp_context=mp.get_context("fork")) as ex:
+        n = sum(ex.map(_oracle_worker, [budget_s] * P))
+    el = time.perf_counter() - t0
+    return {"value": p.n_contacts * args.sweeps * n / el, "unit": "contact-iter/s", "cores": P, "kind": "oracle",
+            "sample": f"{n} steps x {args.sweeps} sweeps over {P} single-thread oracle processes on the "
+                      f"128x128 cloth input, {el:.1f} s"}
+
+
+def cpu_baseline(args, p, budget_s):
+    import oracle
     L = args.sweeps
     t0 = time.perf_counter()
     n = 0
     while True:
-        oracle_mod.vfpi(p, max_iters=L, fixed_iters=True)
+        oracle.vfpi(p, max_iters=L, fixed_iters=True)
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -285,6 +424,68 @@ def cpu_baseline(args, p, oracle_mod, budget_s):
     return {"value": p.n_contacts * L * n / el, "unit": "contact-iter/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} steps x {L} sweeps of the FP64 oracle (NumPy/SciPy, single thread) on the same "
                       f"128x128 cloth input, {el:.1f} s"}
+
+
+def cpu_context(args, scenes, batched_sample=None, adjoint_step=None):
+    """Oracle timings the paper's comparisons call for: V-FPI (plain and
+    Chebyshev) against PGS on the Delassus operator on the 10x10 cloth and
+    the paper-size FEM block; the oracle forward and adjoint of one converged
+    64x64 cloth step; a sample of the batched environments in FP64 with the
+    GPU FP32 result's relative error."""
+    import numpy as np
+    import oracle
+    from oracle.adjoint import adjoint as oracle_adjoint
+    from oracle.chebyshev import vfpi_chebyshev
+    from oracle.delassus import delassus, pgs
+
+    def rel(x, y):
+        ny = np.linalg.norm(y)
+        return float(np.linalg.norm(np.asarray(x) - y) / ny) if ny > 0 else float(np.abs(x).max(initial=0.0))
+
+    out = {}
+    for key, make in (("cloth10", lambda: scenes.cloth_cfg1(args.seed)),
+                      ("fem16x16x4", lambda: scenes.fem_ctx(args.seed))):
+        sc, x, v = make()
+        q = sc.assemble(x, v)
+        rows = []
+        for tol in (1e-4, 1e-6):
+            t0 = time.perf_counter()
+            f = oracle.vfpi(q, max_iters=100000, tol=tol)
+            t1 = time.perf_counter()
+            g = vfpi_chebyshev(q, max_iters=100000, tol=tol, l_s=10)
+            t2 = time.perf_counter()
+            rows.append({"tol": tol, "vfpi_iters": f["iters"], "vfpi_s": t1 - t0,
+                         "vfpi_cheby_iters": g["iters"], "vfpi_cheby_s": t2 - t1})
+        t0 = time.perf_counter()
+        dl = delassus(q)
+        t_d = time.perf_counter() - t0
+        for r in rows:
+            t0 = time.perf_counter()
+            h = pgs(q, tol=r["tol"], max_sweeps=5000, dl=dl)
+            r.update(pgs_sweeps=h["sweeps"], pgs_s=time.perf_counter() - t0 + t_d)
+        out[key] = {"n_nodes": q.n_nodes, "n_contacts": q.n_contacts, "delassus_s": t_d, "runs": rows}
+    if adjoint_step is not None:
+        q, gv = adjoint_step
+        t0 = time.perf_counter()
+        f = oracle.vfpi(q, max_iters=100000, tol=1e-13)
+        t1 = time.perf_counter()
+        a = oracle_adjoint(q, f, gv, None, tol=1e-13)
+        t2 = time.perf_counter()
+        out["adjoint_step_cloth64"] = {"fwd_s": t1 - t0, "bwd_s": t2 - t1, "bwd_over_fwd": (t2 - t1) / (t1 - t0),
+                                       "fwd_sweeps": f["iters"], "bwd_sweeps": a.get("iters")}
+    if batched_sample:
+        errs, t = [], 0.0
+        for e, vg, lg in batched_sample:
+            t0 = time.perf_counter()
+            f = oracle.vfpi(e, max_iters=args.sweeps, fixed_iters=True)
+            t += time.perf_counter() - t0
+            errs.append({"n_nodes": e.n_nodes, "n_contacts": e.n_contacts, "rel_err_v": rel(vg, f["v"]),
+                         "rel_err_lambda": rel(lg, f["lam"].ravel()) if e.n_contacts else 0.0})
+        out["batched_sample"] = {"envs": len(batched_sample), "oracle_env_steps_per_s": len(batched_sample) / t,
+                                 "cores": 1, "max_rel_err": max(max(r["rel_err_v"], r["rel_err_lambda"])
+                                                                for r in errs),
+                                 "per_env": errs}
+    return out
 
 
 def main():
@@ -300,6 +501,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-soft", action="store_true", help="skip the FEM and 10x10 cloth legs")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the convergence runs (tolerances, Chebyshev, paper-size FEM block)")
     ap.add_argument("--batched-variant", type=int, default=0)
     ap.add_argument("--rollout-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -311,11 +514,19 @@ def main():
 
     import torch
 
-    import paper_2201_09212_amd as vf
     import scenes
 
+    sc, x, v = scenes.cloth_cfg2(args.seed)
+    p = sc.assemble(x, v)
+    args._cloth128 = p
+    multicore = None
+    if not args.no_cpu:
+        multicore = cpu_multicore(args, p, args.cpu_seconds)
+
+    import paper_2201_09212_amd as vf
+
     torch.cuda.set_device(0)
-    p, r = plain_bench(args, torch, vf, scenes)
+    p, r = plain_bench(args, torch, vf, scenes, p=p)
     out = {
         "metric": METRIC, "value": r["value"], "unit": "contact-iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -325,8 +536,10 @@ def main():
         "hbm_gbps": r["roofline"]["achieved"], "hbm_frac": r["roofline"]["frac"],
         "sweep_us": r["sweep_us"], "setup_ms": r["setup_ms"], "solve_ms": r["solve_ms"], "variant": r["variant"],
         "dof_iters_per_s": p.n * args.sweeps * args.steps / (r["ms_per_step"] * args.steps * 1e-3),
+        "solve_ms_median": r["solve_ms_median"], "solve_ms_p90": r["solve_ms_p90"],
         "roofline": r["roofline"],
     }
+    out["roofline"]["measured_copy_gbps"] = copy_peak(torch)
     if not args.no_soft:
         # the other single-instance workloads: the FEM soft block and the 10x10 cloth
         for key, make, var in (("fem", lambda: scenes.fem_cfg3(args.seed), 5 | (5 << 8)),
@@ -340,13 +553,18 @@ def main():
                         "contact_iters_per_s": rq["value"], "sweep_us": rq["sweep_us"], "variant": var,
                         "hbm_gbps": rq["roofline"]["achieved"], "hbm_frac": rq["roofline"]["frac"],
                         "kernel": rq["roofline"]["kernel"]}
+    if not args.no_context:
+        out["context"] = context_bench(args, torch, vf, scenes)
     if not args.no_batched:
         out["batched"] = batched_bench(args, torch, vf, scenes)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, torch, vf, scenes)
+    sample = out["batched"].pop("_sample") if "batched" in out else None
+    adj = out["adjoint"].pop("_cpu") if "adjoint" in out else None
     if not args.no_cpu:
-        import oracle
-        out["cpu_baseline"] = cpu_baseline(args, p, oracle, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args, p, args.cpu_seconds)
+        out["cpu_baseline_multicore"] = multicore
+        out["cpu_context"] = cpu_context(args, scenes, sample, adj)
     if args.copy_calibration:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
