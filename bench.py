@@ -542,16 +542,17 @@ def main():
     out["roofline"]["measured_copy_gbps"] = copy_peak(torch)
     if not args.no_soft:
         # the other single-instance workloads: the FEM soft block and the 10x10 cloth
-        for key, make, var in (("fem", lambda: scenes.fem_cfg3(args.seed), 5 | (5 << 8)),
-                               ("cloth10", lambda: scenes.cloth_cfg1(args.seed), 5 | (2 << 8))):
+        for key, make, var, tn in (("fem", lambda: scenes.fem_cfg3(args.seed), 5 | (5 << 8), "fem"),
+                                   ("cloth10", lambda: scenes.cloth_cfg1(args.seed), 5 | (2 << 8), None)):
             sc_, x_, v_ = make()
             q = sc_.assemble(x_, v_)
-            _, rq = plain_bench(args, torch, vf, scenes, p=q, variant=var, traffic_name=None)
+            _, rq = plain_bench(args, torch, vf, scenes, p=q, variant=var, traffic_name=tn)
             out[key] = {"workload": {"fem": "FEM block 64x64x16 cells, 5 tets/cell, FP64",
                                      "cloth10": "10x10 cloth landing on a plane, FP64"}[key],
                         "n_nodes": q.n_nodes, "nnzb": q.nnzb, "n_contacts": q.n_contacts,
                         "contact_iters_per_s": rq["value"], "sweep_us": rq["sweep_us"], "variant": var,
                         "hbm_gbps": rq["roofline"]["achieved"], "hbm_frac": rq["roofline"]["frac"],
+                        "traffic": rq["roofline"]["traffic"], "dram_gbps": rq["roofline"]["dram_gbps"],
                         "kernel": rq["roofline"]["kernel"]}
     if not args.no_context:
         out["context"] = context_bench(args, torch, vf, scenes)

@@ -132,11 +132,14 @@ typedef struct {
   double  alpha_user;    /* VFPI_W_USER_SCALAR only                             */
   int32_t reuse_w;       /* 1: keep the row sums a_dd, ||A_d*||^2 of the previous
                             call on this context (W reuse across steps, Sec. IV-C) */
-  int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16.
+  int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16
+                            | LDS levels << 24.
                             vfpi_step kinds: 1 grid, lane per node; 2 grid, lane per row;
                             3, 4 the same in one workgroup; 5 grid, the node's first
-                            block levels of A in registers (refused with VFPI_E_OPTS when
-                            it needs more than one workgroup per CU).  0 = library
+                            block levels of A in registers and the next ones in LDS
+                            (LDS levels: 0 when rows average more than 9 blocks, 1 off,
+                            2 on; refused with VFPI_E_OPTS when the grid needs more
+                            than one workgroup per CU).  0 = library
                             default: kind 5 with the fewest chunk slots (2, 4, 5, 6, 8)
                             that fit, else kind 1 (BB: kind 3 up to 1024 nodes, else 1).
                             vfpi_step_backward: 0 or 5 register-resident (S-contacts),

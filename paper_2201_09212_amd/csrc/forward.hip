@@ -330,13 +330,14 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
 // Register-resident variant of the persistent kernel (variant kind 5): each
 // workgroup owns at most NW chunks (one pass), so a lane keeps, for the whole
 // step, its node's first KC block levels of A (values and columns), b, W, the
-// contact record, and its own iterate v^l (which it wrote itself).  A sweep
-// gathers the neighbours' v (coherent loads when COH, i.e. more than one
-// workgroup), streams the levels beyond KC, runs the epilogue, and writes
-// v^{l+1} through LDS so every wave stores whole cache lines; lambda and the
-// tape are written once, after the last sweep.  Same arithmetic and order as
-// the streaming kernel.
-template <int NW, int KC, bool COH, bool CH>
+// contact record, and its own iterate v^l (which it wrote itself).  The next
+// KL levels are kept in LDS, so rows longer than KC blocks (solid meshes) do
+// not stream them either.  A sweep gathers the neighbours' v (coherent loads
+// when COH, i.e. more than one workgroup), streams the levels beyond KC + KL
+// in groups of U, runs the epilogue, and writes v^{l+1} through LDS so every
+// wave stores whole cache lines; lambda and the tape are written once, after
+// the last sweep.  Same arithmetic and order as the streaming kernel.
+template <int NW, int KC, int KL, int U, bool COH, bool CH>
 __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   // Registers hold what every sweep streams through the FMA chains: A's first
   // KC levels, the gathered neighbour values and the node's own iterate.  The
@@ -350,6 +351,8 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   __shared__ double s_bw[NW][6][64];      // b (3), W (3)
   __shared__ double s_cr[NW][kPack][64];  // contact record of the lane's node
   __shared__ double s_lam[NW][6][64];     // lambda, lambda* of the last sweep
+  __shared__ double s_al[KL > 0 ? NW : 1][KL > 0 ? KL : 1][9][64];  // levels KC..KC+KL-1
+  __shared__ int s_cl[KL > 0 ? NW : 1][KL > 0 ? KL : 1][64];
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
   const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -390,6 +393,19 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       col[k] = d.scol[q + pos];
 #pragma unroll
       for (int e = 0; e < 9; ++e) av[k][e] = d.sval[9 * q + (int64_t)e * ck + pos];
+    }
+    off += ck;
+  }
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    const uint64_t m = ballot(KC + k < nk);
+    const int ck = __popcll(m);
+    if (KC + k < nk) {
+      const int pos = lanes_below(m, lane);
+      const int64_t q = base + off;
+      s_cl[slot][k][lane] = d.scol[q + pos];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) s_al[slot][k][e][lane] = d.sval[9 * q + (int64_t)e * ck + pos];
     }
     off += ck;
   }
@@ -439,7 +455,32 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
       }
     }
-    spmv_rows3_from<double, COH, (NW >= 8 ? 2 : 1)>(d.scol, d.sval, vcur, base, nk, lane, KC, off_tail, Av);
+    // LDS levels, two at a time (both gathers in flight before the products)
+#pragma unroll
+    for (int k0 = 0; k0 < KL; k0 += 2) {
+      double xl[2][3];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = k0 + u;
+        if (k < KL && KC + k < nk) {
+          const double* xp = vcur + 3 * (int64_t)s_cl[slot][k][lane];
+          xl[u][0] = ldv<COH>(xp);
+          xl[u][1] = ldv<COH>(xp + 1);
+          xl[u][2] = ldv<COH>(xp + 2);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = k0 + u;
+        if (k < KL && KC + k < nk) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            Av[r] += s_al[slot][k][3 * r][lane] * xl[u][0] + s_al[slot][k][3 * r + 1][lane] * xl[u][1] +
+                     s_al[slot][k][3 * r + 2][lane] * xl[u][2];
+        }
+      }
+    }
+    spmv_rows3_from<double, COH, U>(d.scol, d.sval, vcur, base, nk, lane, KC + KL, off_tail, Av);
     double th2 = 0.0;
     double vn[3] = {0.0, 0.0, 0.0};
     if (act) {
@@ -540,6 +581,7 @@ struct Variant {
   int kind;   // 1: grid TPN=1, 2: grid TPN=3, 3: single workgroup TPN=1, 4: single workgroup TPN=3
   int nw;     // chunk slots per workgroup
   int grid;   // workgroup cap (0 = one per CU)
+  int lds;    // kind 5: LDS levels 0 = when rows average more than 9 blocks, 1 = off, 2 = on
 };
 
 // Library default (variant 0): the register-resident kernel with the fewest
@@ -551,6 +593,7 @@ Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu, bool bb) {
   x.kind = v & 0xff;
   x.nw = (v >> 8) & 0xff;
   x.grid = (v >> 16) & 0xff;
+  x.lds = (v >> 24) & 0x3;
   if (x.kind == 0) {
     const int64_t nch = ((int64_t)n_nodes + 63) / 64;
     const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
@@ -607,8 +650,9 @@ hipError_t launch_bb(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, 
 
 // Register-resident kernel: one pass per workgroup, so the grid must cover
 // every chunk with at most NW chunks per workgroup; refused (invalid value)
-// when the problem needs more than one workgroup per CU.
-template <int NW, int KC>
+// when the problem needs more than one workgroup per CU.  KC register levels
+// and KL LDS levels per lane; the rest streamed in groups of U levels.
+template <int NW, int KC, int KL, int U>
 hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, hipStream_t st) {
   const int64_t nch = (n_nodes + 63) / 64;
   int64_t g = (nch + NW - 1) / NW;
@@ -622,12 +666,13 @@ hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
   const bool ch = ga.cheby_ls > 0;
   if (g == 1) {  // one workgroup: plain loads, no cooperative launch needed
     if (ch)
-      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, false, true>), dim3(1), dim3(64 * NW), 0, st, ga);
+      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, true>), dim3(1), dim3(64 * NW), 0, st, ga);
     else
-      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, false, false>), dim3(1), dim3(64 * NW), 0, st, ga);
+      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, false>), dim3(1), dim3(64 * NW), 0, st, ga);
     return hipGetLastError();
   }
-  const void* kern = ch ? (const void*)k_vfpi_regs<NW, KC, true, true> : (const void*)k_vfpi_regs<NW, KC, true, false>;
+  const void* kern = ch ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
+                        : (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>;
   return hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * NW), params, 0, st);
 }
 
@@ -647,15 +692,29 @@ hipError_t launch_variant_bb(const Variant& vr, const GridArgs& ga, int num_cu, 
   }
 }
 
-hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int N, hipStream_t stream) {
+hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int N, bool long_rows,
+                          hipStream_t stream) {
   switch (vr.kind) {
-    case 5:
-      return (vr.nw <= 1)   ? launch_regs<1, 9>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 2) ? launch_regs<2, 9>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 4) ? launch_regs<4, 9>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 5) ? launch_regs<5, 4>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 6) ? launch_regs<6, 4>(ga, vr.grid, num_cu, N, stream)
-                            : launch_regs<8, 4>(ga, vr.grid, num_cu, N, stream);
+    case 5: {
+      // (chunk slots, register levels, LDS levels, tail unroll); the LDS
+      // levels use what the per-node constants leave of the 160 KB.  Their
+      // code costs register space even when no row reaches them, so rows of
+      // at most 9 blocks on average (cloth) take the instances without them.
+      const bool kl = vr.lds == 2 || (vr.lds == 0 && long_rows);
+      if (kl)
+        return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1>(ga, vr.grid, num_cu, N, stream)
+               : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1>(ga, vr.grid, num_cu, N, stream)
+               : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1>(ga, vr.grid, num_cu, N, stream)
+               : (vr.nw <= 5) ? launch_regs<5, 4, 3, 2>(ga, vr.grid, num_cu, N, stream)
+               : (vr.nw <= 6) ? launch_regs<6, 4, 2, 2>(ga, vr.grid, num_cu, N, stream)
+                              : launch_regs<8, 4, 0, 2>(ga, vr.grid, num_cu, N, stream);
+      return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 2) ? launch_regs<2, 9, 0, 1>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 4) ? launch_regs<4, 9, 0, 1>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 5) ? launch_regs<5, 4, 0, 2>(ga, vr.grid, num_cu, N, stream)
+             : (vr.nw <= 6) ? launch_regs<6, 4, 0, 2>(ga, vr.grid, num_cu, N, stream)
+                            : launch_regs<8, 4, 0, 2>(ga, vr.grid, num_cu, N, stream);
+    }
     case 1:
       return (vr.nw <= 1)   ? launch_grid<1, 1>(ga, vr.grid, num_cu, N, false, stream)
              : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, num_cu, N, false, stream)
@@ -766,7 +825,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   Variant vr = decode_variant(opts->variant, N, ctx->num_cu, bb);
   if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
   vfpi_mark(ctx, 1, stream);
-  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream) : launch_variant(vr, ga, ctx->num_cu, N, stream);
+  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream) : launch_variant(vr, ga, ctx->num_cu, N, A->nnzb > 9 * (int64_t)N, stream);
   if (e == hipErrorInvalidValue) return VFPI_E_OPTS;
   if (e == hipErrorNotSupported) return VFPI_E_UNSUPPORTED;
   vfpi_mark(ctx, 2, stream);

@@ -14,7 +14,7 @@ from tests.gpu_util import gpu_step, rel, say, solver_for, upload
 pytestmark = pytest.mark.gpu
 TOL = 1e-9
 
-# kind | chunk slots << 8 | workgroup cap << 16
+# kind | chunk slots << 8 | workgroup cap << 16 | LDS levels (kind 5: 1 off, 2 on) << 24
 VARIANTS = {
     "wg1_node16": 3,
     "wg1_node4": 3 | (4 << 8),
@@ -34,6 +34,10 @@ VARIANTS = {
     "regs_node6": 5 | (6 << 8),
     "regs_node8": 5 | (8 << 8),
     "regs_node1_grid16": 5 | (1 << 8) | (16 << 16),
+    "regs_node2_lds_on": 5 | (2 << 8) | (2 << 24),
+    "regs_node4_lds_on": 5 | (4 << 8) | (2 << 24),
+    "regs_node5_lds_off": 5 | (5 << 8) | (1 << 24),
+    "regs_node1_lds_off": 5 | (1 << 8) | (1 << 24),
 }
 
 CASES = [(1, 1), (5, 0), (5, 5), (63, 20), (64, 64), (65, 30), (130, 77), (700, 300)]
@@ -104,6 +108,27 @@ def test_fem_full_size():
     p = sc.assemble(x, v)
     for variant in (0, 1 | (4 << 8), 2, 1 | (2 << 8), 5 | (5 << 8), 5 | (6 << 8), 5 | (8 << 8)):
         _compare(p, 20, variant)
+
+
+@pytest.mark.parametrize("variant", [k for k in VARIANTS if k.startswith("regs")])
+def test_long_rows_register_lds_and_streamed_levels(variant):
+    """Rows of 4 to 34 blocks (S- and D-contacts): each register-resident
+    instance keeps the first levels in registers, the next ones in LDS and
+    streams the rest."""
+    for n, nc, nd in ((700, 300, 0), (130, 60, 20)):
+        p = scenes.random_problem(n, nc, 7 * n + nc, degree=18.0, phi_scale=0.5, n_d_contacts=nd)
+        assert np.diff(p.row_ptr).max() > 17
+        for L in (1, 9):
+            _compare(p, L, VARIANTS[variant])
+
+
+def test_fem_paper_size_block():
+    """16 x 16 x 4 cells: rows of up to 19 blocks, more than the register and
+    LDS levels of the one- and two-slot register-resident kernels."""
+    sc, x, v = scenes.fem_ctx(0)
+    p = sc.assemble(x, v)
+    for variant in (0, 1 | (2 << 8), 3, 5 | (1 << 8), 5 | (2 << 8), 5 | (4 << 8), 5 | (5 << 8)):
+        _compare(p, 30, variant)
 
 
 def test_inclined_plane_analytic_on_gpu():
