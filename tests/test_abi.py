@@ -69,3 +69,35 @@ def test_missing_library_fails_loudly(tmp_path):
             _abi.load(str(tmp_path / "nope.so"))
         finally:
             _abi._lib = _abi._lib_saved
+
+
+def test_header_layout_matches_binding(tmp_path):
+    """The descriptor structs as a C compiler lays them out from the header:
+    every field's offset and every struct's size equal the Python binding's
+    (a C program that only includes the header; nothing runs on a GPU)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    hip_inc = "/opt/rocm/include"
+    if gcc is None or not os.path.isdir(hip_inc):
+        pytest.skip("needs gcc and the HIP headers")
+    structs = [_abi.vfpi_bsr, _abi.vfpi_contacts, _abi.vfpi_opts, _abi.vfpi_stats]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "vfpi.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append(f'  printf("{n} sizeof %zu\\n", sizeof({n}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", "-D__HIP_PLATFORM_AMD__", f"-I{os.path.join(ROOT, 'include')}",
+                    f"-I{hip_inc}", str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for st in structs:
+        n = st.__name__
+        assert got[(n, "sizeof")] == ctypes.sizeof(st), n
+        for f, _ in st._fields_:
+            assert got[(n, f)] == getattr(st, f).offset, (n, f)
