@@ -362,7 +362,7 @@ def context_bench(args, torch, vf, scenes):
     sc, x, v = scenes.fem_ctx(args.seed)
     q = sc.assemble(x, v)
     return {
-        "cloth128_converge": converge_runs(torch, vf, args._cloth128),
+        "cloth128_converge": converge_runs(torch, vf, args._cloth128, fixed=(50, 200)),
         "fem16x16x4": {"n_nodes": q.n_nodes, "dof": q.n, "nnzb": q.nnzb, "n_contacts": q.n_contacts,
                        "runs": converge_runs(torch, vf, q, tols=(1e-4, 1e-5, 1e-6), fixed=(50, 100)),
                        "paper_context": "soft mat, 4438 DOF, i5-7500 4C CPU: 8.65 ms and 39.72 iterations at "
