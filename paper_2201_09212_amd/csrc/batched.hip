@@ -247,6 +247,8 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
   if (Jc->mu2 && opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
   if (opts->reuse_w && ctx->stats_nodes != N) return VFPI_E_OPTS;
+  const int kind = opts->variant & 0xff;
+  if (kind > 3) return VFPI_E_OPTS;
   if (n_env == 0) return VFPI_OK;
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
 
@@ -297,7 +299,6 @@ extern "C" int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* en
   ba.cheby_u = opts->cheby_u == 0.0 ? 1.0 : opts->cheby_u;
   ctx->stats_nodes = N;
 
-  const int kind = opts->variant & 0xff;
   const int nw = (opts->variant >> 8) & 0xff;
   const int grid = (opts->variant >> 16) & 0xff;
   vfpi_mark(ctx, 0, stream);

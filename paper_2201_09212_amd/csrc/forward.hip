@@ -648,19 +648,29 @@ hipError_t launch_bb(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, 
   return launch_persistent(k_vfpi_bb<NW>, 64 * NW, NW, ga, grid_req, num_cu, n_nodes, single, st);
 }
 
-// Register-resident kernel: one pass per workgroup, so the grid must cover
-// every chunk with at most NW chunks per workgroup; refused (invalid value)
-// when the problem needs more than one workgroup per CU.  KC register levels
-// and KL LDS levels per lane; the rest streamed in groups of U levels.
-template <int NW, int KC, int KL, int U>
-hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, hipStream_t st) {
+// Chunk slots of the register-resident instance a requested slot count maps to.
+int regs_slots(int nw) { return nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : nw <= 5 ? 5 : nw <= 6 ? 6 : 8; }
+
+// Grid of the register-resident kernel: one pass per workgroup, so the grid
+// must cover every chunk with at most NW chunks per workgroup; -1 when that
+// needs more than one workgroup per CU.
+int64_t regs_grid(int NW, int grid_req, int num_cu, int n_nodes) {
   const int64_t nch = (n_nodes + 63) / 64;
   int64_t g = (nch + NW - 1) / NW;
   const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
   if (grid_req > 0 && grid_req > g) g = grid_req < nch ? grid_req : nch;
   if (g > 8 && g % 8 != 0) g += 8 - g % 8;  // round up: every workgroup still gets <= NW chunks
   if (g > nch) g = nch;
-  if (g > cap) return hipErrorInvalidValue;
+  return g > cap ? -1 : g;
+}
+
+// Register-resident launch (refused with invalid value when the grid does not
+// fit).  KC register levels and KL LDS levels per lane; the rest streamed in
+// groups of U levels.
+template <int NW, int KC, int KL, int U>
+hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, hipStream_t st) {
+  const int64_t g = regs_grid(NW, grid_req, num_cu, n_nodes);
+  if (g < 0) return hipErrorInvalidValue;
   GridArgs arg = ga;
   void* params[] = {&arg};
   const bool ch = ga.cheby_ls > 0;
@@ -754,6 +764,11 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
     VFPI_CHECK_HIP(hipGetLastError());
     return VFPI_OK;
   }
+  // the launch variant is checked before anything is enqueued
+  const Variant vr = decode_variant(opts->variant, N, ctx->num_cu, bb);
+  if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
+  if (bb && vr.kind != 1 && vr.kind != 3) return VFPI_E_UNSUPPORTED;
+  if (!bb && vr.kind == 5 && regs_grid(regs_slots(vr.nw), vr.grid, ctx->num_cu, N) < 0) return VFPI_E_OPTS;
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
 
   TapeView tv = {nullptr, nullptr, nullptr, nullptr};
@@ -822,10 +837,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.amax = reinterpret_cast<const unsigned long long*>(ctx->sync + SY_AMAX);
   ga.tape_w = tv.w;
 
-  Variant vr = decode_variant(opts->variant, N, ctx->num_cu, bb);
-  if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
   vfpi_mark(ctx, 1, stream);
-  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream) : launch_variant(vr, ga, ctx->num_cu, N, A->nnzb > 9 * (int64_t)N, stream);
+  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream)
+                    : launch_variant(vr, ga, ctx->num_cu, N, A->nnzb > 9 * (int64_t)N, stream);
   if (e == hipErrorInvalidValue) return VFPI_E_OPTS;
   if (e == hipErrorNotSupported) return VFPI_E_UNSUPPORTED;
   vfpi_mark(ctx, 2, stream);

@@ -209,6 +209,26 @@ def test_synchronous_argument_errors():
         s2.step(A, b, Jc, v, w_mode="scalar", alpha=0.0)
 
 
+def test_beyond_register_resident_grid():
+    """140,000 nodes (2,188 chunks) need more than one workgroup per CU even
+    with 8 chunk slots: the register-resident launch is refused with
+    VFPI_E_OPTS, and the library default takes the streaming kernel."""
+    p = scenes.random_problem(140000, 20000, 3, degree=5.0, phi_scale=0.5)
+    s = solver_for(p)
+    A, Jc, b, v = upload(p)
+    v_in = v.clone()
+    st = vf.new_stats(1, torch.device("cuda", 0))
+    st.fill_(7)
+    sentinel = st.clone()
+    with pytest.raises(vf.VfpiError, match="invalid option"):
+        s.step(A, b, Jc, v, stats=st, max_iters=3, fixed_iters=True, variant=5 | (8 << 8))
+    torch.cuda.synchronize()
+    # refused before anything was enqueued: v and the stats record untouched
+    assert torch.equal(v, v_in) and torch.equal(st, sentinel)
+    for variant in (0, 1 | (4 << 8)):
+        _compare(p, 3, variant)
+
+
 def test_reuse_w_matches_oracle_with_previous_row_sums():
     sc, x, v = scenes.cloth_cfg1(0)
     p1 = sc.assemble(x, v)
