@@ -8,8 +8,9 @@
 //
 // Barrier + residual reduction without read-modify-write atomics: for its
 // k-th synchronization a workgroup first drains its own stores, then
-// publishes its partial sum in slot[k & 1][lb] with a tag derived from k in
-// the 8 low mantissa bits (the partial keeps 44 significant bits).  Every
+// publishes its partial sum in slot[k & 1][lb] (one slot per 256 bytes) with
+// a tag derived from k in the 8 low mantissa bits (the partial keeps 44
+// significant bits).  Every
 // workgroup polls all G slots of that parity (one slot per thread, in
 // parallel) until each carries the tag, and sums them in slot order: every
 // workgroup gets the same bits, hence the same convergence decision, without
@@ -50,14 +51,14 @@ VFPI_DEV double untag(uint64_t b) { return __builtin_bit_cast(double, b & ~0xffu
 // the fixed-order sum of all workgroups' partials in every thread.
 VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, double* s_red) {
   const unsigned tag = sync_tag(seq);
-  uint64_t* sl = slots + (seq & 1) * (int64_t)kMaxGridSlots;
+  uint64_t* sl = slots + (seq & 1) * (int64_t)kMaxGridSlots * kSlotPad;
   drain();
   __syncthreads();
-  if (threadIdx.x == 0) st_relaxed(sl + lb, tagged(x, tag));
+  if (threadIdx.x == 0) st_relaxed(sl + (int64_t)lb * kSlotPad, tagged(x, tag));
   double acc = 0.0;
   for (int k = threadIdx.x; k < G; k += blockDim.x) {
     uint64_t b;
-    while (((b = ld_relaxed(sl + k)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
+    while (((b = ld_relaxed(sl + (int64_t)k * kSlotPad)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
     acc += untag(b);
   }
   return block_sum(acc, s_red);
