@@ -14,6 +14,9 @@ resident in HBM.  Prints one JSON line:
   fem, cloth10 the FEM soft block and the 10x10 cloth, fixed sweeps
   context      sweeps and time to theta < tol (plain and Chebyshev) on the
                128x128 cloth and the paper-size FEM block
+  extensions   per-sweep cost of the proximal operator, the invertible
+               contact, anisotropic friction, Chebyshev, BB1, node-node
+               contacts and virtual nodes
   batched      batched FP32 environments (env-steps/s), when enabled
   adjoint      backward/forward time ratio, when enabled
   cpu_context  oracle V-FPI vs PGS (Delassus), the oracle adjoint step, and
@@ -354,6 +357,77 @@ def adjoint_bench(args, torch, vf, scenes):
             "workload": "cloth64x64 on plane, FP64, converged to 1e-13, checkpoint every 10 steps"}
 
 
+def extensions_bench(args, torch, vf, scenes, p):
+    """Per-sweep cost of the paper's extensions at a fixed 100 sweeps, each
+    next to the plain strict sweep of the same run: on the 128x128 cloth the
+    proximal operator, the invertible contact (omega), anisotropic friction
+    (mu2 = mu / 2), Chebyshev acceleration and BB1 step sizes; node-node
+    contacts on two colliding 64x64 cloths; virtual nodes (eq. vnode) for
+    particles on the 10x10 cloth, with the system build timed as well."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    L = 100
+
+    def timed(prob_or_dev, opt, Jc_override=None, reps=5):
+        A, b, Jc, vv, lam, stats = prob_or_dev
+        Jc = Jc_override or Jc
+        s = vf.Solver(A.n_nodes, A.nnzb, Jc.n_contacts)
+        v0 = vv.clone()
+        vf.vfpi_timing_enable(s.ctx, True)
+        ms = []
+        for _ in range(reps + 1):
+            vv.copy_(v0)
+            s.step(A, b, Jc, vv, lam, stats=stats, max_iters=L, fixed_iters=True, **opt)
+            ms.append(vf.vfpi_timing_read(s.ctx)[1])
+        vf.vfpi_timing_enable(s.ctx, False)
+        st = vf.read_stats(stats)[0]
+        assert st["iters"] == L and st["status"] == 1, st
+        s.close()
+        vv.copy_(v0)
+        return dist(ms[1:])["median"] * 1e3 / L
+
+    out = {}
+    cl = upload(torch, vf, p)
+    crp, ccol, cval = p.jc_bsr()
+    Jc_aniso = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, device=dev, mu2=0.5 * np.asarray(p.mu))
+    base = timed(cl, {})
+    rows = {"strict": base,
+            "proximal (f3)": timed(cl, dict(projection="proximal")),
+            "invertible, omega 1e-3 (f3)": timed(cl, dict(omega=1e-3)),
+            "anisotropic, mu2 = mu/2 (f4)": timed(cl, {}, Jc_override=Jc_aniso),
+            "Chebyshev l_s 10 (f1)": timed(cl, dict(cheby_ls=10)),
+            "BB1 step sizes": timed(cl, dict(w_mode="bb1"))}
+    out["cloth128"] = {k: {"sweep_us": v, "contact_iters_per_s": p.n_contacts / (v * 1e-6), "vs_strict": v / base}
+                       for k, v in rows.items()}
+    q = scenes.cloth_pair_collision(args.seed, side=64)
+    t = timed(upload(torch, vf, q), {})
+    out["d_contacts_pair64 (f2)"] = {"n_nodes": q.n_nodes, "nnzb": q.nnzb, "n_contacts": q.n_contacts,
+                                    "sweep_us": t, "contact_iters_per_s": q.n_contacts / (t * 1e-6)}
+    vs = scenes.particles_on_cloth(args.seed)
+    A_o = vf.bsr_from_arrays(vs.n_o, vs.row_ptr, vs.col_idx, vs.val, device=dev)
+    b_o = torch.as_tensor(vs.b, device=dev)
+    v_o = torch.as_tensor(vs.v0, device=dev)
+    jp, jc, jv = (torch.as_tensor(a) for a in (vs.jv_ptr, vs.jv_col, vs.jv_val))
+    build = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, b, v = vf.vnode_augment(A_o, b_o, v_o, jp, jc, jv, 1e4)
+        torch.cuda.synchronize()
+        build.append((time.perf_counter() - t0) * 1e3)
+    pj = scenes.Problem(n_nodes=A.n_nodes, row_ptr=np.zeros(A.n_nodes + 1), col_idx=np.zeros(0),
+                        val=np.zeros((0, 3, 3)), b=np.zeros(3 * A.n_nodes), v0=np.zeros(3 * A.n_nodes),
+                        c_node=vs.c_node, c_node_j=vs.c_node_j, R=vs.R, phi=vs.phi, mu=vs.mu)
+    crp, ccol, cval = pj.jc_bsr()
+    Jv = vf.contacts_from_arrays(crp, ccol, cval, vs.phi, vs.mu, device=dev)
+    lam = torch.empty(3 * Jv.n_contacts, dtype=torch.float64, device=dev)
+    t = timed((A, b, Jv, v, lam, vf.new_stats(1, dev)), {})
+    out["virtual_nodes_particles_on_cloth10 (f2)"] = {
+        "n_nodes": A.n_nodes, "n_virtual": vs.n_v, "n_contacts": Jv.n_contacts, "k_v": 1e4,
+        "system_build_ms_host_incl": dist(build[1:])["median"], "sweep_us": t}
+    return out
+
+
 def context_bench(args, torch, vf, scenes):
     """Convergence to theta < 1e-4 / 1e-6 (plain and Chebyshev) on the 128x128
     cloth and on the paper-size FEM block (16x16x4 cells, 4,335 DOF), the
@@ -556,6 +630,7 @@ def main():
                         "kernel": rq["roofline"]["kernel"]}
     if not args.no_context:
         out["context"] = context_bench(args, torch, vf, scenes)
+        out["extensions"] = extensions_bench(args, torch, vf, scenes, p)
     if not args.no_batched:
         out["batched"] = batched_bench(args, torch, vf, scenes)
     if not args.no_adjoint:

@@ -427,7 +427,9 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
   for (int e = 0; e < 6; ++e) s_lam[slot][e][lane] = 0.0;
   const bool isd = m >= 0 && is_dcontact(d, m);
-  const bool owner = !isd || d.cpair[2 * (int64_t)m] == i;  // reports lambda
+  const int64_t pi = isd ? d.cpair[2 * (int64_t)m] : -1, pj = isd ? d.cpair[2 * (int64_t)m + 1] : -1;
+  const bool owner = !isd || pi == i;  // reports lambda
+  const bool has_d = d.cpair != nullptr;  // the same in every workgroup
   double vp[3] = {vo[0], vo[1], vo[2]};  // v^{l-1} (Chebyshev only; v^0 = v^1)
   int br = BR_OPEN;
   double* vcur = a.v_user;
@@ -484,22 +486,47 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     spmv_rows3_from<double, COH, U>(d.scol, d.sval, vcur, base, nk, lane, KC + KL, off_tail, Av);
     double th2 = 0.0;
     double vn[3] = {0.0, 0.0, 0.0};
+    double vs[3] = {0.0, 0.0, 0.0};
     if (act) {
-      double vs[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         vs[r] = vo[r] - s_bw[slot][3 + r][lane] * (Av[r] - s_bw[slot][r][lane]);
         vn[r] = vs[r];
       }
-      if (isd) {
-        double lam[3], ls[3];
-        (void)dcontact_node<double, COH>(d, vcur, d.w, 0.0, 0.0, i, m, vs, vn, lam, ls, br);
+    }
+    if (has_d) {
+      // node-node contacts in two phases: the nodes of D pairs publish v*,
+      // and after a grid barrier both nodes of a pair read the same two
+      // values, so they form the same lambda
+      if (act && isd) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) stv<COH>(a.avbuf + 3 * i + r, vs[r]);
+      }
+      grid_barrier(a.slots, G, lb, 2 * l - 1, s_red);
+      if (act && isd) {
+        ContactRec<double> cr;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) cr.R[e] = s_cr[slot][e][lane];
+        cr.phi = s_cr[slot][9][lane];
+        cr.mu = s_cr[slot][10][lane];
+        cr.g = s_cr[slot][11][lane];
+        cr.mu2 = s_cr[slot][12][lane];
+        double eta[3], lam[3], ls[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) eta[r] = ldv<COH>(a.avbuf + 3 * pi + r) - ldv<COH>(a.avbuf + 3 * pj + r);
+        br = contact_solve<double>(cr, eta[0], eta[1], eta[2], d.proj, lam, ls);
+        const double sg = owner ? 1.0 : -1.0;  // +W R^T lambda on node i, -W R^T lambda on node j
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
+          const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
+          vn[r] = vs[r] + sg * s_bw[slot][3 + r][lane] * F;
           s_lam[slot][r][lane] = lam[r];
           s_lam[slot][3 + r][lane] = ls[r];
         }
-      } else if (m >= 0) {
+      }
+    }
+    if (act) {
+      if (m >= 0 && !isd) {
         ContactRec<double> cr;
 #pragma unroll
         for (int e = 0; e < 9; ++e) cr.R[e] = s_cr[slot][e][lane];
@@ -543,8 +570,8 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     for (int r = 0; r < 3; ++r) vo[r] = vn[r];
     th2 = block_sum(th2, s_red);
     double theta;
-    const bool stop =
-        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red, &theta);
+    const bool stop = grid_residual_step(a.slots, G, lb, has_d ? 2 * l : l, th2, l, a.max_iters, a.fixed, a.tol,
+                                         a.stats, s_red, &theta);
     double* t = vcur;
     vcur = vnext;
     vnext = t;

@@ -55,7 +55,7 @@ def test_d_contacts_with_other_options(opts):
         ref = vfpi_chebyshev(p, max_iters=L, fixed_iters=True, l_s=o["cheby_ls"], u=o["cheby_u"])
     else:
         ref = oracle.vfpi(p, max_iters=L, fixed_iters=True, **o)
-    for var in (1 | (2 << 8), 3 | (16 << 8)):
+    for var in (0, 1 | (2 << 8), 3 | (16 << 8)):  # 0: the register-resident kernel (BB: its own kernel)
         v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, variant=var, **opts)
         ev, el = rel(v, ref["v"]), rel(lam, ref["lam"])
         say(f"  random700_d {opts} variant {var:#x}: rel_v={ev:.2e} rel_lam={el:.2e}")
