@@ -345,8 +345,38 @@ VFPI_DEV void block_sum4_int(int& a, int& b, int& c, int* ired) {
 // Fixed-order sum over a workgroup (deterministic): wave butterfly, then the
 // per-wave totals summed in wave order by thread 0.  Result valid in all
 // threads.  `red` is __shared__ scratch of >= blockDim/64 doubles.
+// One DPP move of a double (two 32-bit halves); lanes whose source lies
+// outside the pattern, or whose row is masked off, read 0.
+template <int CTRL, int ROW_MASK>
+VFPI_DEV double dpp_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a full wave, returned in every lane: an inclusive
+// scan inside each row of 16 lanes (row_shr 1, 2, 4, 8), then the row totals
+// carried forward by row_bcast 15 (into rows 1, 3) and row_bcast 31 (into
+// rows 2, 3), so lane 63 holds the total, read back as a scalar.  Register
+// moves only, where a shuffle butterfly goes through LDS six times.
+VFPI_DEV double wave_sum(double x) {
+  x += dpp_f64<0x111, 0xf>(x);
+  x += dpp_f64<0x112, 0xf>(x);
+  x += dpp_f64<0x114, 0xf>(x);
+  x += dpp_f64<0x118, 0xf>(x);
+  x += dpp_f64<0x142, 0xa>(x);
+  x += dpp_f64<0x143, 0xc>(x);
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Workgroup sum (every thread calls; full waves), the same bits in every
+// thread.
 VFPI_DEV double block_sum(double x, double* red) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  x = wave_sum(x);
   int wv = threadIdx.x >> 6;
   int nw = (blockDim.x + 63) >> 6;
   __syncthreads();
