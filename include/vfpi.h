@@ -141,7 +141,7 @@ typedef struct {
                             2 on; refused with VFPI_E_OPTS when the grid needs more
                             than one workgroup per CU).  0 = library
                             default: kind 5 with the fewest chunk slots (2, 4, 5, 6, 8)
-                            that fit, else kind 1 (BB: kind 3 up to 1024 nodes, else 1).
+                            that fit, else kind 1 (also with BB step sizes).
                             vfpi_step_backward: 0 or 5 register-resident (S-contacts),
                             1 streaming, 3 one workgroup.  Batched kinds: see below. */
   int32_t cheby_ls;      /* 0: off; l_s >= 1: Chebyshev acceleration (Alg. 3):
@@ -190,7 +190,7 @@ int64_t vfpi_tape_bytes(int32_t n_nodes, int32_t n_contacts);
  *           receives what vfpi_step_backward needs
  * Errors: VFPI_E_NULL, VFPI_E_SHAPE (also Jc->nnzb > 2 n_c), VFPI_E_OPTS,
  * VFPI_E_CAPACITY, VFPI_E_UNSUPPORTED (BB modes with Chebyshev or with launch
- * kinds other than 1 and 3; mu2 with VFPI_PROJ_PROXIMAL), VFPI_E_HIP. */
+ * kinds other than 1, 3 and 5; mu2 with VFPI_PROJ_PROXIMAL), VFPI_E_HIP. */
 int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc,
               double* v, double* lambda, const vfpi_opts* opts, vfpi_stats* stats,
               void* tape, hipStream_t stream);

@@ -337,8 +337,11 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
 // when COH, i.e. more than one workgroup), streams the levels beyond KC + KL
 // in groups of U, runs the epilogue, and writes v^{l+1} through LDS so every
 // wave stores whole cache lines; lambda and the tape are written once, after
-// the last sweep.  Same arithmetic and order as the streaming kernel.
-template <int NW, int KC, int KL, int U, bool COH, bool CH>
+// the last sweep.  Same arithmetic and order as the streaming kernel.  BB:
+// Barzilai-Borwein step sizes (W = alpha^l I, see k_vfpi_bb), with the node's
+// own v^{l-1} and A v^{l-1} kept in registers and one more grid reduction
+// (the three dot products) per sweep.
+template <int NW, int KC, int KL, int U, bool COH, bool CH, bool BB = false>
 __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   // Registers hold what every sweep streams through the FMA chains: A's first
   // KC levels, the gathered neighbour values and the node's own iterate.  The
@@ -437,6 +440,9 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   Cheby ch;
   ch.ls = CH ? a.cheby_ls : 0;
   ch.u = a.cheby_u;
+  // BB: alpha^1 from the Gershgorin bound; v^{l-1} and A v^{l-1} of the own node
+  double alpha = BB ? 1.0 / __builtin_bit_cast(double, (uint64_t)*a.amax) : 0.0;
+  double vq[3] = {0.0, 0.0, 0.0}, aq[3] = {0.0, 0.0, 0.0};
   for (int l = 1;; ++l) {
     const double nu = CH ? ch.next_nu(l) : 1.0;
     double xs[KC][3];
@@ -484,13 +490,36 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       }
     }
     spmv_rows3_from<double, COH, U>(d.scol, d.sval, vcur, base, nk, lane, KC + KL, off_tail, Av);
+    if (BB) {
+      // s = v^l - v^{l-1}, z = A v^l - A v^{l-1}: s's, s'z, z'z over the grid
+      if (l >= 2) {
+        double dots[3] = {0.0, 0.0, 0.0};
+        if (act) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const double s = vo[r] - vq[r], z = Av[r] - aq[r];
+            dots[0] += s * s;
+            dots[1] += s * z;
+            dots[2] += z * z;
+          }
+        }
+        grid_sum3(a.slots + kBBSlotOffset, G, lb, l - 1, dots, s_red);
+        if (!a.bb2 && dots[0] > 0.0 && dots[1] > 0.0) alpha = dots[0] / dots[1];
+        else if (a.bb2 && dots[1] > 0.0 && dots[2] > 0.0) alpha = dots[1] / dots[2];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        vq[r] = vo[r];
+        aq[r] = Av[r];
+      }
+    }
     double th2 = 0.0;
     double vn[3] = {0.0, 0.0, 0.0};
     double vs[3] = {0.0, 0.0, 0.0};
     if (act) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        vs[r] = vo[r] - s_bw[slot][3 + r][lane] * (Av[r] - s_bw[slot][r][lane]);
+        vs[r] = vo[r] - (BB ? alpha : s_bw[slot][3 + r][lane]) * (Av[r] - s_bw[slot][r][lane]);
         vn[r] = vs[r];
       }
     }
@@ -509,7 +538,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         for (int e = 0; e < 9; ++e) cr.R[e] = s_cr[slot][e][lane];
         cr.phi = s_cr[slot][9][lane];
         cr.mu = s_cr[slot][10][lane];
-        cr.g = s_cr[slot][11][lane];
+        cr.g = BB ? 2.0 * alpha + a.omega : s_cr[slot][11][lane];  // gamma = w_i + w_j (+ omega)
         cr.mu2 = s_cr[slot][12][lane];
         double eta[3], lam[3], ls[3];
 #pragma unroll
@@ -519,7 +548,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
-          vn[r] = vs[r] + sg * s_bw[slot][3 + r][lane] * F;
+          vn[r] = vs[r] + sg * (BB ? alpha : s_bw[slot][3 + r][lane]) * F;
           s_lam[slot][r][lane] = lam[r];
           s_lam[slot][3 + r][lane] = ls[r];
         }
@@ -532,14 +561,14 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         for (int e = 0; e < 9; ++e) cr.R[e] = s_cr[slot][e][lane];
         cr.phi = s_cr[slot][9][lane];
         cr.mu = s_cr[slot][10][lane];
-        cr.g = s_cr[slot][11][lane];
+        cr.g = BB ? alpha + a.omega : s_cr[slot][11][lane];
         cr.mu2 = s_cr[slot][12][lane];
         double lam[3], ls[3];
         br = contact_solve<double>(cr, vs[0], vs[1], vs[2], d.proj, lam, ls);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
-          vn[r] = vs[r] + s_bw[slot][3 + r][lane] * F;
+          vn[r] = vs[r] + (BB ? alpha : s_bw[slot][3 + r][lane]) * F;
           s_lam[slot][r][lane] = lam[r];
           s_lam[slot][3 + r][lane] = ls[r];
         }
@@ -597,6 +626,10 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       if (a.tape_v) a.tape_v[3 * i + r] = vo[r];
     }
   }
+  if (BB && act && a.tape_w) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a.tape_w[3 * i + r] = alpha;
+  }
 }
 
 }  // namespace vfpi
@@ -614,9 +647,8 @@ struct Variant {
 
 // Library default (variant 0): the register-resident kernel with the fewest
 // chunk slots per workgroup that still fits one workgroup per CU; the
-// streaming kernels when the problem is larger (or for BB step sizes, which
-// have their own kernel in kinds 1 and 3).
-Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu, bool bb) {
+// streaming kernel (kind 1) when the problem is larger.
+Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu) {
   Variant x;
   x.kind = v & 0xff;
   x.nw = (v >> 8) & 0xff;
@@ -625,19 +657,15 @@ Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu, bool bb) {
   if (x.kind == 0) {
     const int64_t nch = ((int64_t)n_nodes + 63) / 64;
     const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
-    if (bb) {
-      x.kind = (n_nodes <= 1024) ? 3 : 1;
-    } else {
-      x.kind = 1;
-      for (int nw : {2, 4, 5, 6, 8}) {
-        int64_t g = (nch + nw - 1) / nw;
-        if (g > 8 && g % 8 != 0) g += 8 - g % 8;
-        if (g > nch) g = nch;
-        if (g <= cap) {
-          x.kind = 5;
-          if (x.nw == 0) x.nw = nw;
-          break;
-        }
+    x.kind = 1;
+    for (int nw : {2, 4, 5, 6, 8}) {
+      int64_t g = (nch + nw - 1) / nw;
+      if (g > 8 && g % 8 != 0) g += 8 - g % 8;
+      if (g > nch) g = nch;
+      if (g <= cap) {
+        x.kind = 5;
+        if (x.nw == 0) x.nw = nw;
+        break;
       }
     }
   }
@@ -695,29 +723,65 @@ int64_t regs_grid(int NW, int grid_req, int num_cu, int n_nodes) {
 // Register-resident launch (refused with invalid value when the grid does not
 // fit).  KC register levels and KL LDS levels per lane; the rest streamed in
 // groups of U levels.
-template <int NW, int KC, int KL, int U>
+template <int NW, int KC, int KL, int U, bool BB>
 hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, hipStream_t st) {
   const int64_t g = regs_grid(NW, grid_req, num_cu, n_nodes);
   if (g < 0) return hipErrorInvalidValue;
   GridArgs arg = ga;
   void* params[] = {&arg};
-  const bool ch = ga.cheby_ls > 0;
-  if (g == 1) {  // one workgroup: plain loads, no cooperative launch needed
-    if (ch)
-      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, true>), dim3(1), dim3(64 * NW), 0, st, ga);
-    else
-      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, false>), dim3(1), dim3(64 * NW), 0, st, ga);
-    return hipGetLastError();
+  const void* kern;
+  if constexpr (BB) {  // no Chebyshev with BB step sizes
+    if (g == 1) {      // one workgroup: plain loads, no cooperative launch needed
+      hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, false, true>), dim3(1), dim3(64 * NW), 0, st, ga);
+      return hipGetLastError();
+    }
+    kern = (const void*)k_vfpi_regs<NW, KC, KL, U, true, false, true>;
+  } else {
+    const bool ch = ga.cheby_ls > 0;
+    if (g == 1) {
+      if (ch)
+        hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, true>), dim3(1), dim3(64 * NW), 0, st, ga);
+      else
+        hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, false>), dim3(1), dim3(64 * NW), 0, st, ga);
+      return hipGetLastError();
+    }
+    kern = ch ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
+              : (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>;
   }
-  const void* kern = ch ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
-                        : (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>;
   return hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * NW), params, 0, st);
 }
 
-// Barzilai-Borwein step sizes: the two-phase kernel, grid (kind 1) or one
-// workgroup (kind 3); the other kinds do not implement it.
-hipError_t launch_variant_bb(const Variant& vr, const GridArgs& ga, int num_cu, int N, hipStream_t stream) {
+// Kind 5: (chunk slots, register levels, LDS levels, tail unroll); the LDS
+// levels use what the per-node constants leave of the 160 KB.  Their code
+// costs register space even when no row reaches them, so rows of at most 9
+// blocks on average (cloth) take the instances without them.
+template <bool BB>
+hipError_t launch_kind5(const Variant& vr, const GridArgs& ga, int num_cu, int N, bool long_rows,
+                        hipStream_t stream) {
+  const bool kl = vr.lds == 2 || (vr.lds == 0 && long_rows);
+  if (kl)
+    return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, stream)
+           : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, stream)
+           : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1, BB>(ga, vr.grid, num_cu, N, stream)
+           : (vr.nw <= 5) ? launch_regs<5, 4, 3, 2, BB>(ga, vr.grid, num_cu, N, stream)
+           : (vr.nw <= 6) ? launch_regs<6, 4, 2, 2, BB>(ga, vr.grid, num_cu, N, stream)
+                          : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream);
+  return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, stream)
+         : (vr.nw <= 2) ? launch_regs<2, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, stream)
+         : (vr.nw <= 4) ? launch_regs<4, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, stream)
+         : (vr.nw <= 5) ? launch_regs<5, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream)
+         : (vr.nw <= 6) ? launch_regs<6, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream)
+                        : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream);
+}
+
+// Barzilai-Borwein step sizes: the register-resident kernel (kind 5) or the
+// two-phase streaming kernel, grid (kind 1) or one workgroup (kind 3); the
+// other kinds do not implement it.
+hipError_t launch_variant_bb(const Variant& vr, const GridArgs& ga, int num_cu, int N, bool long_rows,
+                             hipStream_t stream) {
   switch (vr.kind) {
+    case 5:
+      return launch_kind5<true>(vr, ga, num_cu, N, long_rows, stream);
     case 1:
       return (vr.nw <= 1)   ? launch_bb<1>(ga, vr.grid, num_cu, N, false, stream)
              : (vr.nw <= 2) ? launch_bb<2>(ga, vr.grid, num_cu, N, false, stream)
@@ -733,26 +797,8 @@ hipError_t launch_variant_bb(const Variant& vr, const GridArgs& ga, int num_cu, 
 hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int N, bool long_rows,
                           hipStream_t stream) {
   switch (vr.kind) {
-    case 5: {
-      // (chunk slots, register levels, LDS levels, tail unroll); the LDS
-      // levels use what the per-node constants leave of the 160 KB.  Their
-      // code costs register space even when no row reaches them, so rows of
-      // at most 9 blocks on average (cloth) take the instances without them.
-      const bool kl = vr.lds == 2 || (vr.lds == 0 && long_rows);
-      if (kl)
-        return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1>(ga, vr.grid, num_cu, N, stream)
-               : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1>(ga, vr.grid, num_cu, N, stream)
-               : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1>(ga, vr.grid, num_cu, N, stream)
-               : (vr.nw <= 5) ? launch_regs<5, 4, 3, 2>(ga, vr.grid, num_cu, N, stream)
-               : (vr.nw <= 6) ? launch_regs<6, 4, 2, 2>(ga, vr.grid, num_cu, N, stream)
-                              : launch_regs<8, 4, 0, 2>(ga, vr.grid, num_cu, N, stream);
-      return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 2) ? launch_regs<2, 9, 0, 1>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 4) ? launch_regs<4, 9, 0, 1>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 5) ? launch_regs<5, 4, 0, 2>(ga, vr.grid, num_cu, N, stream)
-             : (vr.nw <= 6) ? launch_regs<6, 4, 0, 2>(ga, vr.grid, num_cu, N, stream)
-                            : launch_regs<8, 4, 0, 2>(ga, vr.grid, num_cu, N, stream);
-    }
+    case 5:
+      return launch_kind5<false>(vr, ga, num_cu, N, long_rows, stream);
     case 1:
       return (vr.nw <= 1)   ? launch_grid<1, 1>(ga, vr.grid, num_cu, N, false, stream)
              : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, num_cu, N, false, stream)
@@ -793,10 +839,10 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
     return VFPI_OK;
   }
   // the launch variant is checked before anything is enqueued
-  const Variant vr = decode_variant(opts->variant, N, ctx->num_cu, bb);
+  const Variant vr = decode_variant(opts->variant, N, ctx->num_cu);
   if (vr.kind < 1 || vr.kind > 5) return VFPI_E_OPTS;
-  if (bb && vr.kind != 1 && vr.kind != 3) return VFPI_E_UNSUPPORTED;
-  if (!bb && vr.kind == 5 && regs_grid(regs_slots(vr.nw), vr.grid, ctx->num_cu, N) < 0) return VFPI_E_OPTS;
+  if (bb && vr.kind != 1 && vr.kind != 3 && vr.kind != 5) return VFPI_E_UNSUPPORTED;
+  if (vr.kind == 5 && regs_grid(regs_slots(vr.nw), vr.grid, ctx->num_cu, N) < 0) return VFPI_E_OPTS;
   VFPI_CHECK_HIP(hipSetDevice(ctx->device));
 
   TapeView tv = {nullptr, nullptr, nullptr, nullptr};
@@ -866,8 +912,9 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.tape_w = tv.w;
 
   vfpi_mark(ctx, 1, stream);
-  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, stream)
-                    : launch_variant(vr, ga, ctx->num_cu, N, A->nnzb > 9 * (int64_t)N, stream);
+  const bool long_rows = A->nnzb > 9 * (int64_t)N;
+  hipError_t e = bb ? launch_variant_bb(vr, ga, ctx->num_cu, N, long_rows, stream)
+                    : launch_variant(vr, ga, ctx->num_cu, N, long_rows, stream);
   if (e == hipErrorInvalidValue) return VFPI_E_OPTS;
   if (e == hipErrorNotSupported) return VFPI_E_UNSUPPORTED;
   vfpi_mark(ctx, 2, stream);

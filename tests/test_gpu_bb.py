@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 
 # kind | chunk slots << 8 | workgroup cap << 16
 VARIANTS = {"grid_node1": 1 | (1 << 8), "grid_node2": 1 | (2 << 8), "grid_node4_cap8": 1 | (4 << 8) | (8 << 16),
-            "wg1_node4": 3 | (4 << 8), "wg1_node16": 3 | (16 << 8)}
+            "wg1_node4": 3 | (4 << 8), "wg1_node16": 3 | (16 << 8), "default": 0,
+            "regs_node1": 5 | (1 << 8), "regs_node2": 5 | (2 << 8), "regs_node5": 5 | (5 << 8),
+            "regs_node8": 5 | (8 << 8), "regs_node2_lds_on": 5 | (2 << 8) | (2 << 24)}
 
 
 def _problems():
@@ -42,7 +44,7 @@ def test_bb_fixed_sweeps_parity(variant, mode):
 @pytest.mark.parametrize("mode", ["bb1", "bb2"])
 def test_bb_one_eigenspace_closed_form(mode):
     p, x = scenes.two_level_diagonal(300, 0)
-    for var in (VARIANTS["grid_node1"], VARIANTS["wg1_node4"]):
+    for var in (VARIANTS["grid_node1"], VARIANTS["wg1_node4"], VARIANTS["regs_node2"]):
         v, _, st, _ = gpu_step(p, max_iters=3, fixed_iters=True, w_mode=mode, variant=var)
         say(f"  two_level300 {mode} variant {var:#x}: |v - x*| = {np.abs(v.ravel() - x).max():.2e}")
         assert np.abs(v.ravel() - x).max() <= 1e-14 and st["theta"] <= 1e-14
@@ -69,6 +71,6 @@ def test_bb_unsupported_combinations():
     A, Jc, b, v = upload(p)
     with pytest.raises(vf.VfpiError, match="not supported"):
         s.step(A, b, Jc, v, w_mode="bb1", cheby_ls=5)
-    for kind in (2, 4, 5):
+    for kind in (2, 4):
         with pytest.raises(vf.VfpiError, match="not supported"):
             s.step(A, b, Jc, v.clone(), w_mode="bb2", variant=kind)
