@@ -553,10 +553,10 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   double* w = static_cast<double*>(ctx->w);
 
   vfpi_mark(ctx, 0, stream);
-  hipLaunchKernelGGL(k_prep, dim3((N + 255) / 256), dim3(256), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync,
+  hipLaunchKernelGGL(k_prep, dim3((N + 63) / 64), dim3(64), 0, stream, N, ctx->cmap, ctx->flags, ctx->sync,
                      ctx->slots, stats);
   if (nc > 0)
-    hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 255) / 256), dim3(256), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
+    hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 63) / 64), dim3(64), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
                        static_cast<const double*>(Jc->mu), nullptr, N, ctx->cmap, cpack, ctx->cpair, ctx->flags,
                        1e-10);
@@ -568,7 +568,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   ra.alpha = 0.0;
   ra.omega = opts->omega;
   const int64_t nch = (N + 63) / 64;
-  hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, stream, N, A->row_ptr, A->col_idx,
+  hipLaunchKernelGGL(k_rows<double>, dim3((unsigned)nch), dim3(64), 0, stream, N, A->row_ptr, A->col_idx,
                      static_cast<const double*>(A->val), ctx->scol, static_cast<double*>(ctx->sval), nullptr, nullptr,
                      ra, tv.w, ctx->cmap, cpack, w, nullptr, grad_v, tv.v,
                      ctx->flags);
