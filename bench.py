@@ -59,11 +59,18 @@ def kernel_name(variant):
 
 
 def kernel_sources_hash():
+    """Hash of the HIP sources with comments and whitespace removed, so that
+    the stored byte counters stay valid across documentation edits but not
+    across code changes."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2201_09212_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(f.encode() + " ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -337,7 +337,10 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
 // when COH, i.e. more than one workgroup), streams the levels beyond KC + KL
 // in groups of U, runs the epilogue, and writes v^{l+1} through LDS so every
 // wave stores whole cache lines; lambda and the tape are written once, after
-// the last sweep.  Same arithmetic and order as the streaming kernel.  BB:
+// the last sweep.  Same arithmetic and order as the streaming kernel, except
+// for node-node contacts: their nodes publish v* and read the pair's v* back
+// after a grid barrier (two phases per sweep) instead of recomputing both
+// rows.  BB:
 // Barzilai-Borwein step sizes (W = alpha^l I, see k_vfpi_bb), with the node's
 // own v^{l-1} and A v^{l-1} kept in registers and one more grid reduction
 // (the three dot products) per sweep.
