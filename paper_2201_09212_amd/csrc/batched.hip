@@ -168,10 +168,13 @@ __global__ void __launch_bounds__(64 * TPN * NW, MW) k_vfpi_batched(BatchArgs a)
         const int64_t c = (int64_t)p * NW + slot;
         const int64_t n0 = n_lo + 64 * c;
         const int cnt = (c < nch) ? (int)min<int64_t>(64, n_hi - n0) : 0;
-        if (TPN == 3)
+        if (TPN == 3) {
           sweep_chunk_row<float>(d, vcur, vnext, n0, cnt, lane, r, s_vs[p & 1][TPN == 3 ? slot : 0], th2, cb);
-        else
-          sweep_chunk_node<float>(d, vcur, vnext, n0, cnt, lane, th2, cb);
+        } else {
+          // levels streamed in groups of 4 with two workgroups per CU, of 2 with one
+          // (fewer registers, and measured faster on the 2048-environment mix)
+          sweep_chunk_node<float, false, (MW == 1 ? 2 : 4)>(d, vcur, vnext, n0, cnt, lane, th2, cb);
+        }
       }
       block_sum4(th2, cb[0], cb[1], cb[2], s_red, s_ired);
       const int o = cb[0], s = cb[1], sl = cb[2];
