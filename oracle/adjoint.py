@@ -20,6 +20,15 @@ and then, with r = J W u + g_lam and q = u - J^T Gamma^{-1} D_P^T r:
     b_bar = W q,   A_bar_ij = -b_bar_i v_j (on the pattern of A),
     phi_bar_m = -(D_P,m^T r_m)_n / gamma_m,   mu_bar_m = (dP_m/dmu)^T r_m.
 
+With the proximal operator (Euclidean projection onto the cone, eq. operator)
+D_P on the slip branch is that of the second-order-cone projection
+P = (n + mu s)/(1 + mu^2) (1, mu t/s): with c = 1/(1 + mu^2), h = t/s and
+a = (n + mu s) c,
+    dP_n/dn = c,  dP_n/dt = mu c h^T,  dP_t/dn = mu c h,
+    dP_t/dt = mu^2 c h h^T + (mu a / s)(I - h h^T),
+    dP_n/dmu = c (s - 2 mu a),  dP_t/dmu = (a + mu dP_n/dmu) h;
+stick is I and open (the polar cone) is 0, as for the strict operator.
+
 ``adjoint`` solves for u by the transposed fixed-point iteration (SciPy
 matvecs); ``adjoint_dense`` solves the same linear system with a dense LU.
 Pins: the two agree; gradients match central finite differences of the
@@ -34,15 +43,31 @@ import scipy.sparse as sp
 from .core import BRANCH_SLIP, BRANCH_STICK, contact_jacobian, system_matrix
 
 
-def projection_jacobians(lam_star, branch, mu):
-    """Per contact: D_P [nc,3,3] and dP/dmu [nc,3]."""
+def projection_jacobians(lam_star, branch, mu, projection="strict"):
+    """Per contact: D_P [nc,3,3] and dP/dmu [nc,3] on the branch taken."""
     nc = lam_star.shape[0]
     DP = np.zeros((nc, 3, 3))
     dmu = np.zeros((nc, 3))
     st = branch == BRANCH_STICK
     DP[st] = np.eye(3)
     sl = np.nonzero(branch == BRANCH_SLIP)[0]
-    if sl.size:
+    if sl.size and projection == "proximal":
+        n = lam_star[sl, 0]
+        t = lam_star[sl, 1:]
+        s = np.linalg.norm(t, axis=1)
+        h = t / s[:, None]
+        m = mu[sl]
+        c = 1.0 / (1.0 + m * m)
+        a = (n + m * s) * c
+        DP[sl, 0, 0] = c
+        DP[sl, 0, 1:] = (m * c)[:, None] * h
+        DP[sl, 1:, 0] = (m * c)[:, None] * h
+        hh = h[:, :, None] * h[:, None, :]
+        DP[sl, 1:, 1:] = (m * m * c)[:, None, None] * hh + (m * a / s)[:, None, None] * (np.eye(2) - hh)
+        da = c * (s - 2.0 * m * a)
+        dmu[sl, 0] = da
+        dmu[sl, 1:] = (a + m * da)[:, None] * h
+    elif sl.size:
         n = lam_star[sl, 0]
         t = lam_star[sl, 1:]
         s = np.linalg.norm(t, axis=1)
@@ -56,9 +81,11 @@ def projection_jacobians(lam_star, branch, mu):
 
 
 def _operators(p, fwd):
+    if getattr(p, "mu2", None) is not None:
+        raise NotImplementedError("the adjoint does not differentiate the elliptic (anisotropic) projection")
     A = system_matrix(p)
     J = contact_jacobian(p)
-    DP, dmu = projection_jacobians(fwd["lam_star"], fwd["branch"], p.mu)
+    DP, dmu = projection_jacobians(fwd["lam_star"], fwd["branch"], p.mu, fwd.get("projection", "strict"))
     DPb = sp.block_diag(list(DP), format="csr") if p.n_contacts else sp.csr_matrix((0, 0))
     ginv = np.repeat(1.0 / fwd["gamma"], 3)
     return A, J, DP, dmu, DPb, ginv

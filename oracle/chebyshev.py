@@ -92,4 +92,4 @@ def vfpi_chebyshev(p, *, max_iters=100, tol=0.0, fixed_iters=False, l_s=10, u=1.
             rho = min(theta / theta_prev, 1.0) if theta_prev else 0.0  # eq. varrho
         theta_prev = theta
     return {"v": v, "lam": lam, "iters": it, "theta": theta, "lam_star": lam_star, "branch": branch, "w": w,
-            "gamma": gamma, "history": hist}
+            "gamma": gamma, "history": hist, "projection": projection}

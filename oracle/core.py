@@ -313,4 +313,5 @@ def vfpi(p, *, max_iters=100, tol=0.0, fixed_iters=False, w_mode="frobenius", w_
         if not fixed_iters and theta < tol:
             break
     return {"v": v, "lam": lam, "iters": it, "theta": theta, "lam_star": lam_star,
-            "branch": branch, "w": w, "gamma": gamma, "alpha": alpha, "history": hist}
+            "branch": branch, "w": w, "gamma": gamma, "alpha": alpha, "history": hist,
+            "projection": projection}

@@ -19,10 +19,11 @@ def _problem(seed):
     return scenes.random_problem(14, 7, seed, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_iterative_adjoint_matches_dense(seed):
+@pytest.mark.parametrize("seed,projection", [(0, "strict"), (1, "strict"), (2, "strict"), (0, "proximal"),
+                                             (2, "proximal")])
+def test_iterative_adjoint_matches_dense(seed, projection):
     p = _problem(seed)
-    f = _fwd(p)
+    f = _fwd(p, projection=projection)
     g = np.random.default_rng(seed)
     gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
     a = adjoint(p, f, gv, gl)
@@ -31,17 +32,21 @@ def test_iterative_adjoint_matches_dense(seed):
         np.testing.assert_allclose(a[k], d[k], rtol=0, atol=1e-10 * (1 + np.abs(d[k]).max()))
 
 
-def _loss(p, gv, gl, omega=0.0):
-    f = _fwd(p, omega=omega)
+def _loss(p, gv, gl, omega=0.0, projection="strict"):
+    f = _fwd(p, omega=omega, projection=projection)
     return gv @ f["v"] + gl @ f["lam"].ravel(), f["branch"]
 
 
-@pytest.mark.parametrize("seed,omega", [(0, 0.0), (1, 0.0), (2, 0.0), (0, 0.02), (1, 0.3)])
-def test_adjoint_matches_central_differences(seed, omega):
+@pytest.mark.parametrize("seed,omega,projection", [(0, 0.0, "strict"), (1, 0.0, "strict"), (2, 0.0, "strict"),
+                                                   (0, 0.02, "strict"), (1, 0.3, "strict"),
+                                                   (0, 0.0, "proximal"), (1, 0.02, "proximal"),
+                                                   (2, 0.3, "proximal")])
+def test_adjoint_matches_central_differences(seed, omega, projection):
     """With omega > 0 (invertible contact, eq. invt) the same adjoint applies
-    with gamma + omega in the contact step."""
+    with gamma + omega in the contact step; with the proximal operator D_P is
+    the cone projection's Jacobian."""
     p = _problem(seed)
-    f = _fwd(p, omega=omega)
+    f = _fwd(p, omega=omega, projection=projection)
     g = np.random.default_rng(100 + seed)
     gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
     grad = adjoint(p, f, gv, gl)
@@ -49,8 +54,8 @@ def test_adjoint_matches_central_differences(seed, omega):
     checked = 0
 
     def fd(make):
-        lp, bp = _loss(make(+eps), gv, gl, omega)
-        lm, bm = _loss(make(-eps), gv, gl, omega)
+        lp, bp = _loss(make(+eps), gv, gl, omega, projection)
+        lm, bm = _loss(make(-eps), gv, gl, omega, projection)
         if not (np.array_equal(bp, f["branch"]) and np.array_equal(bm, f["branch"])):
             return None  # the active set changed inside +-eps: not differentiable there
         return (lp - lm) / (2 * eps)
@@ -90,13 +95,14 @@ def test_adjoint_matches_central_differences(seed, omega):
     assert checked >= 10
 
 
-def test_gradient_independent_of_w():
+@pytest.mark.parametrize("projection", ["strict", "proximal"])
+def test_gradient_independent_of_w(projection):
     p = _problem(3)
     g = np.random.default_rng(7)
     gv = g.normal(size=p.n)
-    f1 = _fwd(p)
+    f1 = _fwd(p, projection=projection)
     alpha = oracle.core.gershgorin_alpha(oracle.system_matrix(p))
-    f2 = _fwd(p, w_mode="scalar", alpha_user=alpha)
+    f2 = _fwd(p, w_mode="scalar", alpha_user=alpha, projection=projection)
     a1, a2 = adjoint(p, f1, gv), adjoint(p, f2, gv)
     for k in ("b", "phi", "mu"):
         np.testing.assert_allclose(a1[k], a2[k], atol=1e-8 * (1 + np.abs(a1[k]).max()))
@@ -123,3 +129,34 @@ def test_sliding_particle_closed_form():
         mu_bar += ad["mu"][0]
         v_bar_next_b = ad["b"]
     np.testing.assert_allclose(mu_bar, -h * h * g * np.cos(a) * N * (N + 1) / 2, rtol=1e-10)
+
+
+def test_proximal_projection_jacobian_vs_differences():
+    """D_P and dP/dmu of the cone projection (proximal operator) against
+    central differences of oracle.core.project_proximal, on points well
+    inside each branch."""
+    from oracle.adjoint import projection_jacobians
+    from oracle.core import project_proximal
+    g = np.random.default_rng(11)
+    pts, mus = [], []
+    while len(pts) < 60:
+        mu = g.uniform(0.1, 1.5)
+        ls = g.normal(size=3)
+        s = np.hypot(ls[1], ls[2])
+        # stay away from the branch boundaries s = mu n and mu s = -n
+        if abs(s - mu * ls[0]) < 0.05 or abs(mu * s + ls[0]) < 0.05 or s < 0.05:
+            continue
+        pts.append(ls)
+        mus.append(mu)
+    lam_star, mu = np.array(pts), np.array(mus)
+    _, branch = project_proximal(lam_star, mu)
+    assert set(branch.tolist()) == {0, 1, 2}
+    DP, dmu = projection_jacobians(lam_star, branch, mu, "proximal")
+    eps = 1e-7
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = eps
+        num = (project_proximal(lam_star + e, mu)[0] - project_proximal(lam_star - e, mu)[0]) / (2 * eps)
+        np.testing.assert_allclose(DP[:, :, k], num, atol=1e-7)
+    num = (project_proximal(lam_star, mu + eps)[0] - project_proximal(lam_star, mu - eps)[0]) / (2 * eps)
+    np.testing.assert_allclose(dmu, num, atol=1e-7)
