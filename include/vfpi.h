@@ -224,9 +224,10 @@ int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* env_node_off,
  *   opts      max_iters / tol of the adjoint's own fixed-point iteration
  * The adjoint u solves u = g + (I - A W) G^T u with G = I - W J^T D_P Gamma^-1 J
  * (D_P = projection Jacobian of the last sweep), by transposed sweeps that
- * reuse the forward's layout; D-contacts and opts.omega (which must equal
- * the forward's) are supported.  Errors as vfpi_step, plus VFPI_E_NO_TAPE for
- * tape == NULL and VFPI_E_UNSUPPORTED for VFPI_PROJ_PROXIMAL or mu2. */
+ * reuse the forward's layout; D-contacts, opts.omega and opts.projection
+ * (both of which must equal the forward's) are supported.  Errors as
+ * vfpi_step, plus VFPI_E_NO_TAPE for tape == NULL and VFPI_E_UNSUPPORTED for
+ * mu2 (the elliptic projection is not differentiated). */
 int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc,
                        const void* tape, const double* grad_v, const double* grad_lambda,
                        double* grad_b, double* grad_A_val, double* grad_phi, double* grad_mu,

@@ -2,7 +2,7 @@
 
 ``vfpi_solve`` runs ``vfpi_step`` (FP64, to tolerance) in the forward pass and
 ``vfpi_step_backward`` (the hand-written adjoint of the converged step, with
-the active branch of every contact's strict projection) in the backward pass;
+the active branch of every contact's projection) in the backward pass;
 gradients flow to A's values, b, phi and mu.  The warm start carries no
 gradient (the converged solution does not depend on it).
 
@@ -59,10 +59,12 @@ DEFAULT_BWD = dict(max_iters=100000, tol=1e-13)
 def vfpi_solve(solver, A_val, b, phi, mu, v_warm, row_ptr, col_idx, n_nodes, c_node, R, fwd_opts=None,
                bwd_opts=None):
     """Differentiable V-FPI step; returns (v, lambda, stats tensor).  The
-    backward pass uses the forward's contact regularization (omega)."""
+    backward pass uses the forward's contact regularization (omega) and
+    projection operator."""
     fwd = dict(fwd_opts or DEFAULT_FWD)
     bwd = dict(bwd_opts or DEFAULT_BWD)
     bwd["omega"] = fwd.get("omega", 0.0)
+    bwd["projection"] = fwd.get("projection", "strict")
     return VfpiStepFn.apply(A_val, b, phi, mu, v_warm, solver, row_ptr, col_idx, n_nodes, c_node, R, fwd, bwd)
 
 

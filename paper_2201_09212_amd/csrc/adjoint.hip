@@ -3,7 +3,7 @@
 //
 // The step's fixed-point map (Sec. IV, Lemma 1 framing) is
 //   f(v) = v* + W J^T P(-Gamma^-1 (J v* + phi e1)),  v* = v - W (A v - b),
-// with P the strict projection (eq. operator).  Holding W constant (the fixed
+// with P the strict or the proximal projection (eq. operator).  Holding W constant (the fixed
 // point does not depend on it, consistency remark of Sec. III-B) and writing
 // D_P for P's Jacobian on the branch taken in the last sweep, G = I - W J^T D_P
 // Gamma^-1 J, the adjoint u of a loss with gradients (g_v, g_lam) solves
@@ -53,10 +53,18 @@ struct AdjArgs {
   const int32_t* flags;
   vfpi_stats* stats;
   uint64_t* slots;
+  int32_t proj;  // the forward's projection (VFPI_PROJ_*)
 };
 
-// y = D_P^T x for the contact's branch; *dmu = (dP/dmu)^T x.
-VFPI_DEV void dp_transpose(const double* ls, int br, double mu, const double x[3], double y[3], double* dmu) {
+// y = D_P^T x for the contact's branch; *dmu = (dP/dmu)^T x.  Slip, strict
+// operator: dl_n/dn = 1, dl_t/dn = mu h, dl_t/dt = (mu n / s)(I - h h^T),
+// dl_t/dmu = n h with (n, t) = lambda*, s = |t|, h = t / s.  Slip, proximal
+// operator (projection onto the cone, P = a (1, mu h), a = (n + mu s) c,
+// c = 1 / (1 + mu^2)): the symmetric D_P = [c, mu c h^T; mu c h,
+// mu^2 c h h^T + (mu a / s)(I - h h^T)], dP_n/dmu = c (s - 2 mu a),
+// dP_t/dmu = (a + mu dP_n/dmu) h.
+VFPI_DEV void dp_transpose(const double* ls, int br, double mu, int proj, const double x[3], double y[3],
+                           double* dmu) {
   if (br == BR_STICK) {
     y[0] = x[0];
     y[1] = x[1];
@@ -73,6 +81,18 @@ VFPI_DEV void dp_transpose(const double* ls, int br, double mu, const double x[3
   const double s = sqrt(t1 * t1 + t2 * t2);
   const double h1 = t1 / s, h2 = t2 / s;
   const double ht = h1 * x[1] + h2 * x[2];
+  if (proj == VFPI_PROJ_PROXIMAL) {
+    const double c = 1.0 / (1.0 + mu * mu);
+    const double al = (n + mu * s) * c;
+    const double z = c * (x[0] + mu * ht);
+    const double kp = mu * al / s;
+    y[0] = z;
+    y[1] = mu * h1 * z + kp * (x[1] - h1 * ht);
+    y[2] = mu * h2 * z + kp * (x[2] - h2 * ht);
+    const double da = c * (s - 2.0 * mu * al);
+    *dmu = da * x[0] + (al + mu * da) * ht;
+    return;
+  }
   const double k = mu * n / s;
   y[0] = x[0] + mu * ht;
   y[1] = k * (x[1] - h1 * ht);
@@ -91,7 +111,7 @@ VFPI_DEV void gt_node(const AdjArgs& a, int64_t i, int m, const double u[3], dou
   const double f = a.w[3 * i] / R[11];
   double x[3], y[3], dmu;
   for (int k = 0; k < 3; ++k) x[k] = (R[3 * k] * u[0] + R[3 * k + 1] * u[1] + R[3 * k + 2] * u[2]) * f;
-  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
   for (int r = 0; r < 3; ++r) out[r] -= R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
 }
 
@@ -105,7 +125,7 @@ VFPI_DEV void gt_pair(const AdjArgs& a, int m, bool first, const double ui[3], c
   for (int k = 0; k < 3; ++k)
     x[k] = (R[3 * k] * ui[0] + R[3 * k + 1] * ui[1] + R[3 * k + 2] * ui[2]) * fi -
            (R[3 * k] * uj[0] + R[3 * k + 1] * uj[1] + R[3 * k + 2] * uj[2]) * fj;
-  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
   const double* u = first ? ui : uj;
   for (int r = 0; r < 3; ++r) {
     const double f = R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
@@ -174,7 +194,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
       if (m >= 0) {
         const double* R = a.cpack + kPack * (int64_t)m;
         double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
-        dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+        dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
         const double gi = (adj_isd(a, m) && a.cpair[2 * (int64_t)m] != i) ? -1.0 / R[11] : 1.0 / R[11];
         for (int r = 0; r < 3; ++r) e[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
       }
@@ -300,7 +320,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         for (int k = 0; k < 3; ++k)
           rr[k] -= R[3 * k] * (wj * uj[0]) + R[3 * k + 1] * (wj * uj[1]) + R[3 * k + 2] * (wj * uj[2]);
       }
-      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], rr, y, &dmu);
+      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, rr, y, &dmu);
       const double gi = 1.0 / R[11];
       const double sg = first ? gi : -gi;
       for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * sg;
@@ -432,7 +452,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     if (m >= 0) {
       const double* R = a.cpack + kPack * (int64_t)m;
       double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
-      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], x, y, &dmu);
+      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
       const double gi = 1.0 / R[11];
       for (int r = 0; r < 3; ++r) e3[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
     }
@@ -496,7 +516,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       rr[k] = R[3 * k] * (wb * uu[0]) + R[3 * k + 1] * (wb * uu[1]) + R[3 * k + 2] * (wb * uu[2]);
       if (a.gl) rr[k] += a.gl[3 * (int64_t)m + k];
     }
-    dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], rr, y, &dmu);
+    dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, rr, y, &dmu);
     const double gi = 1.0 / R[11];
     for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
     a.grad_phi[m] = -y[0] * gi;
@@ -539,7 +559,6 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
     return VFPI_E_NULL;
   if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
   if (opts->max_iters < 0 || !(opts->tol >= 0.0)) return VFPI_E_OPTS;
-  if (opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
   if (Jc->mu2) return VFPI_E_UNSUPPORTED;  // anisotropic friction: no projection Jacobian here
   if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
   if (N == 0) {
@@ -614,6 +633,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   aa.flags = ctx->flags;
   aa.stats = stats;
   aa.slots = ctx->slots;
+  aa.proj = opts->projection;
 
   const int kind = opts->variant & 0xff;
   const int grid_req = (opts->variant >> 16) & 0xff;

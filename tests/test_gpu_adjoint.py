@@ -15,14 +15,15 @@ from tests.gpu_util import rel, say, upload
 pytestmark = pytest.mark.gpu
 
 
-def gpu_fwd_bwd(p, gv, gl=None, tol=1e-14, want_A=True, variant=0):
+def gpu_fwd_bwd(p, gv, gl=None, tol=1e-14, want_A=True, variant=0, **opt):
     s = vf.Solver(p.n_nodes, p.nnzb, max(p.n_contacts, 1))
     A, Jc, b, v = upload(p)
     tape = s.tape(p.n_nodes, p.n_contacts)
-    lam, st = s.step(A, b, Jc, v, tape=tape, max_iters=200000, tol=tol)
+    lam, st = s.step(A, b, Jc, v, tape=tape, max_iters=200000, tol=tol, **opt)
     gvt = torch.as_tensor(gv, device="cuda")
     glt = None if gl is None else torch.as_tensor(gl, device="cuda")
-    g = s.step_backward(A, Jc, tape, gvt, glt, want_A=want_A, max_iters=200000, tol=1e-13, variant=variant)
+    g = s.step_backward(A, Jc, tape, gvt, glt, want_A=want_A, max_iters=200000, tol=1e-13, variant=variant,
+                        **opt)
     torch.cuda.synchronize()
     out = {k: (t.cpu().numpy() if isinstance(t, torch.Tensor) and k != "stats" else t) for k, t in g.items()}
     out["fwd_stats"] = vf.read_stats(st)[0]
@@ -57,16 +58,38 @@ def test_adjoint_matches_oracle(name, p, with_glam, variant):
         assert e <= 1e-7, (k, e)
 
 
-def test_adjoint_vs_central_differences_of_gpu_forward():
+@pytest.mark.parametrize("opt", [{}, {"projection": "proximal"}, {"projection": "proximal", "omega": 0.05}])
+@pytest.mark.parametrize("variant", [0, 1, 3])
+def test_proximal_adjoint_matches_oracle(variant, opt):
+    """The proximal operator's adjoint (cone projection Jacobian) against the
+    oracle's, with and without the invertible contact; {} is the strict
+    reference of the same problems."""
+    for name, p in list(_cases())[1:]:
+        g = np.random.default_rng(5)
+        gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+        out = gpu_fwd_bwd(p, gv, gl, variant=variant, **opt)
+        fwd = oracle.vfpi(p, max_iters=200000, tol=1e-14, **opt)
+        ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
+        assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
+        assert out["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, out["bwd_stats"]
+        errs = {k: rel(out[k], ref[k]) for k in ("b", "A", "phi", "mu")}
+        slip = int((fwd["branch"] == 2).sum())
+        say(f"  {name} {opt} variant {variant}: {slip} slipping, bwd {out['bwd_stats']['iters']} sweeps, {errs}")
+        for k, e in errs.items():
+            assert e <= 1e-7, (k, e)
+
+
+@pytest.mark.parametrize("opt", [{}, {"projection": "proximal"}])
+def test_adjoint_vs_central_differences_of_gpu_forward(opt):
     p = scenes.random_problem(40, 18, 5, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
     g = np.random.default_rng(4)
     gv = g.normal(size=p.n)
-    out = gpu_fwd_bwd(p, gv)
+    out = gpu_fwd_bwd(p, gv, **opt)
     s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
 
     def loss(q):
         A, Jc, b, v = upload(q)
-        lam, st = s.step(A, b, Jc, v, max_iters=200000, tol=1e-14)
+        lam, st = s.step(A, b, Jc, v, max_iters=200000, tol=1e-14, **opt)
         torch.cuda.synchronize()
         return float(gv @ v.cpu().numpy())
 
