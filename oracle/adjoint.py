@@ -29,6 +29,15 @@ a = (n + mu s) c,
     dP_n/dmu = c (s - 2 mu a),  dP_t/dmu = (a + mu dP_n/dmu) h;
 stick is I and open (the polar cone) is 0, as for the strict operator.
 
+With anisotropic friction (strict operator on the elliptic cone, Sec. III-E)
+the slip branch keeps lambda_n = n and x_i = A_i t_i / (A_i + s), A_i =
+(mu_i n)^2, with s the root of F(s) = sum_i A_i t_i^2 / (A_i + s)^2 - 1.
+Implicit differentiation (D_i = A_i + s, F_s = -2 sum_i A_i t_i^2 / D_i^3):
+    ds = -(sum_i 2 A_i t_i / D_i^2 dt_i + sum_i t_i^2 (s - A_i) / D_i^3 dA_i) / F_s,
+    dx_i = (t_i s / D_i^2) dA_i + (A_i / D_i) dt_i - (x_i / D_i) ds,
+    dA_i = 2 mu_i^2 n dn + 2 mu_i n^2 dmu_i,
+which gives D_P, dP/dmu1 and dP/dmu2 (mu2_bar = (dP/dmu2)^T r).
+
 ``adjoint`` solves for u by the transposed fixed-point iteration (SciPy
 matvecs); ``adjoint_dense`` solves the same linear system with a dense LU.
 Pins: the two agree; gradients match central finite differences of the
@@ -40,18 +49,50 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .core import BRANCH_SLIP, BRANCH_STICK, contact_jacobian, system_matrix
+from .core import BRANCH_SLIP, BRANCH_STICK, contact_jacobian, ellipse_root, system_matrix
 
 
-def projection_jacobians(lam_star, branch, mu, projection="strict"):
-    """Per contact: D_P [nc,3,3] and dP/dmu [nc,3] on the branch taken."""
+def ellipse_jacobian(n, t, mu1, mu2):
+    """Slip branch of the strict operator on the elliptic cone: D_P [3,3],
+    dP/dmu1 [3] and dP/dmu2 [3] at lambda* = (n, t)."""
+    mu = np.array([mu1, mu2])
+    A = (mu * n) ** 2
+    s = ellipse_root(t[0], t[1], mu1 * n, mu2 * n)
+    D = A + s
+    x = A * t / D
+    F_s = -2.0 * np.sum(A * t * t / D ** 3)
+    g_t = 2.0 * A * t / D ** 2
+    g_A = t * t * (s - A) / D ** 3
+    A_n = 2.0 * mu * mu * n          # dA_i / dn
+    A_mu = 2.0 * mu * n * n          # dA_i / dmu_i
+    ds_dn = -np.sum(g_A * A_n) / F_s
+    ds_dt = -g_t / F_s
+    ds_dmu = -g_A * A_mu / F_s
+    DP = np.zeros((3, 3))
+    dmu = np.zeros((2, 3))
+    DP[0, 0] = 1.0
+    for i in range(2):
+        DP[1 + i, 0] = t[i] * s / D[i] ** 2 * A_n[i] - x[i] / D[i] * ds_dn
+        for j in range(2):
+            DP[1 + i, 1 + j] = (A[i] / D[i] if i == j else 0.0) - x[i] / D[i] * ds_dt[j]
+            dmu[j, 1 + i] = (t[i] * s / D[i] ** 2 * A_mu[i] if i == j else 0.0) - x[i] / D[i] * ds_dmu[j]
+    return DP, dmu[0], dmu[1]
+
+
+def projection_jacobians(lam_star, branch, mu, projection="strict", mu2=None):
+    """Per contact: D_P [nc,3,3], dP/dmu [nc,3] and (anisotropic friction)
+    dP/dmu2 [nc,3] on the branch taken; dP/dmu2 is None without mu2."""
     nc = lam_star.shape[0]
     DP = np.zeros((nc, 3, 3))
     dmu = np.zeros((nc, 3))
+    dmu2 = None if mu2 is None else np.zeros((nc, 3))
     st = branch == BRANCH_STICK
     DP[st] = np.eye(3)
     sl = np.nonzero(branch == BRANCH_SLIP)[0]
-    if sl.size and projection == "proximal":
+    if sl.size and mu2 is not None:
+        for m in sl:
+            DP[m], dmu[m], dmu2[m] = ellipse_jacobian(lam_star[m, 0], lam_star[m, 1:], mu[m], mu2[m])
+    elif sl.size and projection == "proximal":
         n = lam_star[sl, 0]
         t = lam_star[sl, 1:]
         s = np.linalg.norm(t, axis=1)
@@ -77,21 +118,23 @@ def projection_jacobians(lam_star, branch, mu, projection="strict"):
         DP[sl, 1:, 0] = m[:, None] * th
         DP[sl, 1:, 1:] = (m * n / s)[:, None, None] * (np.eye(2) - th[:, :, None] * th[:, None, :])
         dmu[sl, 1:] = n[:, None] * th
-    return DP, dmu
+    return DP, dmu, dmu2
 
 
 def _operators(p, fwd):
-    if getattr(p, "mu2", None) is not None:
-        raise NotImplementedError("the adjoint does not differentiate the elliptic (anisotropic) projection")
+    mu2 = getattr(p, "mu2", None)
+    if mu2 is not None and fwd.get("projection", "strict") != "strict":
+        raise ValueError("anisotropic friction is defined for the strict operator only")
     A = system_matrix(p)
     J = contact_jacobian(p)
-    DP, dmu = projection_jacobians(fwd["lam_star"], fwd["branch"], p.mu, fwd.get("projection", "strict"))
+    DP, dmu, dmu2 = projection_jacobians(fwd["lam_star"], fwd["branch"], p.mu, fwd.get("projection", "strict"), mu2)
     DPb = sp.block_diag(list(DP), format="csr") if p.n_contacts else sp.csr_matrix((0, 0))
     ginv = np.repeat(1.0 / fwd["gamma"], 3)
-    return A, J, DP, dmu, DPb, ginv
+    return A, J, DP, (dmu, dmu2), DPb, ginv
 
 
-def _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv):
+def _grads_from_u(p, fwd, u, g_lam, J, DP, dmus, DPb, ginv):
+    dmu, dmu2 = dmus
     w = fwd["w"]
     nc = p.n_contacts
     r = J @ (w * u) + g_lam
@@ -101,14 +144,18 @@ def _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv):
     dpr = np.einsum("mji,mj->mi", DP, rm)           # D_P^T r per contact
     phi_bar = -dpr[:, 0] / fwd["gamma"]
     mu_bar = np.einsum("mi,mi->m", dmu, rm)
+    mu2_bar = None if dmu2 is None else np.einsum("mi,mi->m", dmu2, rm)
     # A_bar on the block pattern: block (i, c) = -b_bar_i v_c^T
     rows = np.repeat(np.arange(p.n_nodes), np.diff(p.row_ptr))
     A_bar = -b_bar.reshape(-1, 3)[rows][:, :, None] * fwd["v"].reshape(-1, 3)[p.col_idx][:, None, :]
-    return {"u": u, "b": b_bar, "A": A_bar, "phi": phi_bar, "mu": mu_bar}
+    out = {"u": u, "b": b_bar, "A": A_bar, "phi": phi_bar, "mu": mu_bar}
+    if mu2_bar is not None:
+        out["mu2"] = mu2_bar
+    return out
 
 
 def adjoint(p, fwd, g_v, g_lam=None, *, tol=1e-14, max_iters=100000):
-    A, J, DP, dmu, DPb, ginv = _operators(p, fwd)
+    A, J, DP, dmus, DPb, ginv = _operators(p, fwd)
     w = fwd["w"]
     nc = p.n_contacts
     g_lam = np.zeros(3 * nc) if g_lam is None else np.asarray(g_lam, dtype=np.float64).ravel()
@@ -129,13 +176,13 @@ def adjoint(p, fwd, g_v, g_lam=None, *, tol=1e-14, max_iters=100000):
         u = u_new
         if theta < tol:
             break
-    out = _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv)
+    out = _grads_from_u(p, fwd, u, g_lam, J, DP, dmus, DPb, ginv)
     out.update(iters=it, theta=theta)
     return out
 
 
 def adjoint_dense(p, fwd, g_v, g_lam=None):
-    A, J, DP, dmu, DPb, ginv = _operators(p, fwd)
+    A, J, DP, dmus, DPb, ginv = _operators(p, fwd)
     w = fwd["w"]
     n, nc = p.n, p.n_contacts
     g_lam = np.zeros(3 * nc) if g_lam is None else np.asarray(g_lam, dtype=np.float64).ravel()
@@ -148,4 +195,4 @@ def adjoint_dense(p, fwd, g_v, g_lam=None):
     IAW = np.eye(n) - Ad @ W
     g_t = g_v - IAW @ (Jd.T @ (Gam_inv @ (DPd.T @ g_lam)))
     u = np.linalg.solve(np.eye(n) - IAW @ G.T, g_t)
-    return _grads_from_u(p, fwd, u, g_lam, J, DP, dmu, DPb, ginv)
+    return _grads_from_u(p, fwd, u, g_lam, J, DP, dmus, DPb, ginv)

@@ -193,19 +193,25 @@ def _ellipse_closest(y1, y2, a, b):
     min |x - y|^2 gives x_i = a_i^2 y_i / (a_i^2 + s) with s > 0 the root of
     sum_i (a_i y_i / (a_i^2 + s))^2 = 1; the left side falls from above 1 at
     s = 0 to at most 1 at s = a |y1| + b |y2|, and brentq brackets it there."""
-    from scipy.optimize import brentq
-
     if a == 0.0 or b == 0.0:
         x1, x2 = min(max(y1, -a), a), min(max(y2, -b), b)
         return x1, x2, (x1 == y1 and x2 == y2)
     if (y1 * b) ** 2 + (y2 * a) ** 2 <= (a * b) ** 2:
         return y1, y2, True
 
+    s = ellipse_root(y1, y2, a, b)
+    return a * a * y1 / (a * a + s), b * b * y2 / (b * b + s), False
+
+
+def ellipse_root(y1, y2, a, b):
+    """The Lagrange multiplier s > 0 of the closest point to (y1, y2) outside
+    the ellipse of semi-axes a, b > 0 (see _ellipse_closest)."""
+    from scipy.optimize import brentq
+
     def F(s):
         return (a * y1 / (a * a + s)) ** 2 + (b * y2 / (b * b + s)) ** 2 - 1.0
 
-    s = brentq(F, 0.0, a * abs(y1) + b * abs(y2), xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
-    return a * a * y1 / (a * a + s), b * b * y2 / (b * b + s), False
+    return brentq(F, 0.0, a * abs(y1) + b * abs(y2), xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
 
 
 def project_strict_aniso(lam_star, mu1, mu2):

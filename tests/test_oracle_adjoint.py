@@ -151,7 +151,7 @@ def test_proximal_projection_jacobian_vs_differences():
     lam_star, mu = np.array(pts), np.array(mus)
     _, branch = project_proximal(lam_star, mu)
     assert set(branch.tolist()) == {0, 1, 2}
-    DP, dmu = projection_jacobians(lam_star, branch, mu, "proximal")
+    DP, dmu, _ = projection_jacobians(lam_star, branch, mu, "proximal")
     eps = 1e-7
     for k in range(3):
         e = np.zeros(3)
@@ -160,3 +160,91 @@ def test_proximal_projection_jacobian_vs_differences():
         np.testing.assert_allclose(DP[:, :, k], num, atol=1e-7)
     num = (project_proximal(lam_star, mu + eps)[0] - project_proximal(lam_star, mu - eps)[0]) / (2 * eps)
     np.testing.assert_allclose(dmu, num, atol=1e-7)
+
+
+def test_ellipse_projection_jacobian_vs_differences():
+    """D_P, dP/dmu1 and dP/dmu2 of the strict operator on the elliptic cone
+    (anisotropic friction) against central differences of
+    oracle.core.project_strict_aniso, on points well inside each branch; and
+    at mu1 = mu2 the ellipse Jacobian equals the disk's."""
+    from oracle.adjoint import ellipse_jacobian, projection_jacobians
+    from oracle.core import project_strict_aniso
+    g = np.random.default_rng(12)
+    pts, m1, m2 = [], [], []
+    while len(pts) < 40:
+        a1, a2 = g.uniform(0.2, 1.2, size=2)
+        ls = g.normal(size=3)
+        if ls[0] < 0.1 and ls[0] > -0.1:
+            continue
+        q = (ls[1] / (a1 * ls[0])) ** 2 + (ls[2] / (a2 * ls[0])) ** 2 if ls[0] > 0 else 9.0
+        if abs(q - 1.0) < 0.1:   # near the ellipse boundary: branch may flip under +-eps
+            continue
+        pts.append(ls)
+        m1.append(a1)
+        m2.append(a2)
+    lam_star, mu1, mu2 = np.array(pts), np.array(m1), np.array(m2)
+    _, branch = project_strict_aniso(lam_star, mu1, mu2)
+    assert set(branch.tolist()) == {0, 1, 2}
+    DP, dmu1, dmu2 = projection_jacobians(lam_star, branch, mu1, "strict", mu2)
+    eps = 1e-7
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = eps
+        num = (project_strict_aniso(lam_star + e, mu1, mu2)[0] - project_strict_aniso(lam_star - e, mu1, mu2)[0]) / (2 * eps)
+        np.testing.assert_allclose(DP[:, :, k], num, atol=2e-7)
+    num = (project_strict_aniso(lam_star, mu1 + eps, mu2)[0] - project_strict_aniso(lam_star, mu1 - eps, mu2)[0]) / (2 * eps)
+    np.testing.assert_allclose(dmu1, num, atol=2e-7)
+    num = (project_strict_aniso(lam_star, mu1, mu2 + eps)[0] - project_strict_aniso(lam_star, mu1, mu2 - eps)[0]) / (2 * eps)
+    np.testing.assert_allclose(dmu2, num, atol=2e-7)
+    # circle: the disk operator's Jacobian, and dP/dmu1 + dP/dmu2 = dP/dmu of the disk
+    ls = np.array([[0.7, 1.1, -0.4]])
+    DPd, dmud, _ = projection_jacobians(ls, np.array([2]), np.array([0.5]))
+    DPe, d1, d2 = ellipse_jacobian(0.7, ls[0, 1:], 0.5, 0.5)
+    np.testing.assert_allclose(DPe, DPd[0], atol=1e-12)
+    np.testing.assert_allclose(d1 + d2, dmud[0], atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 2, 7])
+def test_anisotropic_adjoint_matches_central_differences(seed):
+    """The adjoint with the elliptic cone: b, phi, mu1 and mu2 gradients of a
+    converged step against central differences; the dense solve agrees."""
+    p = _problem(seed)
+    p.mu2 = np.asarray(p.mu) * np.random.default_rng(seed).uniform(0.3, 1.8, size=p.n_contacts)
+    f = _fwd(p)
+    assert (f["branch"] == 2).sum() >= 2
+    g = np.random.default_rng(200 + seed)
+    gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+    grad = adjoint(p, f, gv, gl)
+    dense = adjoint_dense(p, f, gv, gl)
+    for k in ("b", "phi", "mu", "mu2"):
+        np.testing.assert_allclose(grad[k], dense[k], rtol=0, atol=1e-9 * (1 + np.abs(dense[k]).max()))
+    eps = 1e-6
+    checked = 0
+
+    def fd(name, arr_p, arr_m):
+        out = []
+        for arr in (arr_p, arr_m):
+            q = scenes.Problem(**{**p.__dict__, name: arr})
+            fq = _fwd(q)
+            if not np.array_equal(fq["branch"], f["branch"]):
+                return None
+            out.append(gv @ fq["v"] + gl @ fq["lam"].ravel())
+        return (out[0] - out[1]) / (2 * eps)
+
+    for k in g.choice(p.n, 5, replace=False):
+        e = np.zeros(p.n)
+        e[k] = eps
+        val = fd("b", p.b + e, p.b - e)
+        if val is not None:
+            assert abs(val - grad["b"][k]) <= 1e-6 * (1 + abs(val))
+            checked += 1
+    for m in range(p.n_contacts):
+        e = np.zeros(p.n_contacts)
+        e[m] = eps
+        for name in ("phi", "mu", "mu2"):
+            base = np.asarray(getattr(p, name))
+            val = fd(name, base + e, base - e)
+            if val is not None:
+                assert abs(val - grad[name][m]) <= 1e-6 * (1 + abs(val)), (name, m, val, grad[name][m])
+                checked += 1
+    assert checked >= 10
