@@ -36,7 +36,11 @@ Implicit differentiation (D_i = A_i + s, F_s = -2 sum_i A_i t_i^2 / D_i^3):
     ds = -(sum_i 2 A_i t_i / D_i^2 dt_i + sum_i t_i^2 (s - A_i) / D_i^3 dA_i) / F_s,
     dx_i = (t_i s / D_i^2) dA_i + (A_i / D_i) dt_i - (x_i / D_i) ds,
     dA_i = 2 mu_i^2 n dn + 2 mu_i n^2 dmu_i,
-which gives D_P, dP/dmu1 and dP/dmu2 (mu2_bar = (dP/dmu2)^T r).
+which gives D_P, dP/dmu1 and dP/dmu2 (mu2_bar = (dP/dmu2)^T r).  With one
+coefficient zero the ellipse is a segment and P clamps each tangent component
+to [-mu_i n, mu_i n]: a clamped component has dx_i/dn = sign(t_i) mu_i and
+dx_i/dmu_i = sign(t_i) n, a free one dx_i/dt_i = 1; the derivative in the
+zero coefficient is the one-sided one of the opening ellipse (ellipse_jacobian).
 
 ``adjoint`` solves for u by the transposed fixed-point iteration (SciPy
 matvecs); ``adjoint_dense`` solves the same linear system with a dense LU.
@@ -56,6 +60,33 @@ def ellipse_jacobian(n, t, mu1, mu2):
     """Slip branch of the strict operator on the elliptic cone: D_P [3,3],
     dP/dmu1 [3] and dP/dmu2 [3] at lambda* = (n, t)."""
     mu = np.array([mu1, mu2])
+    DP = np.zeros((3, 3))
+    dmu = np.zeros((2, 3))
+    DP[0, 0] = 1.0
+    if mu1 == 0.0 or mu2 == 0.0:
+        # a zero semi-axis: the ellipse is a segment and P clamps each tangent
+        # component to [-mu_i n, mu_i n] on its own
+        for i in range(2):
+            if abs(t[i]) > mu[i] * n:
+                sg = np.sign(t[i])
+                DP[1 + i, 0] = sg * mu[i]
+                dmu[i, 1 + i] = sg * n
+            else:
+                DP[1 + i, 1 + i] = 1.0
+        # the zero coefficient's derivative is one-sided (mu >= 0): the
+        # ellipse's limit as its axis opens.  Past the tip (|t_j| > b) the
+        # closest point stays at the tip to first order; beside the segment
+        # s = a |t_i| / r + O(a^2), r = sqrt(1 - t_j^2 / b^2), so
+        # dx_i/dmu_i = sign(t_i) n r and dx_j/dmu_i = -n t_j |t_i| / (b^2 r).
+        i = 0 if mu1 == 0.0 else 1
+        j = 1 - i
+        dmu[i] = 0.0
+        b = mu[j] * n
+        if b > 0.0 and abs(t[j]) < b:
+            r = np.sqrt(1.0 - (t[j] / b) ** 2)
+            dmu[i, 1 + i] = np.sign(t[i]) * n * r
+            dmu[i, 1 + j] = -n * t[j] * abs(t[i]) / (b * b * r)
+        return DP, dmu[0], dmu[1]
     A = (mu * n) ** 2
     s = ellipse_root(t[0], t[1], mu1 * n, mu2 * n)
     D = A + s
@@ -68,9 +99,6 @@ def ellipse_jacobian(n, t, mu1, mu2):
     ds_dn = -np.sum(g_A * A_n) / F_s
     ds_dt = -g_t / F_s
     ds_dmu = -g_A * A_mu / F_s
-    DP = np.zeros((3, 3))
-    dmu = np.zeros((2, 3))
-    DP[0, 0] = 1.0
     for i in range(2):
         DP[1 + i, 0] = t[i] * s / D[i] ** 2 * A_n[i] - x[i] / D[i] * ds_dn
         for j in range(2):

@@ -196,6 +196,29 @@ def test_ellipse_projection_jacobian_vs_differences():
     np.testing.assert_allclose(dmu1, num, atol=2e-7)
     num = (project_strict_aniso(lam_star, mu1, mu2 + eps)[0] - project_strict_aniso(lam_star, mu1, mu2 - eps)[0]) / (2 * eps)
     np.testing.assert_allclose(dmu2, num, atol=2e-7)
+    # a zero coefficient (segment): the clamp's Jacobian, on both tangents
+    for za, zb in ((0.0, 0.8), (0.6, 0.0)):
+        pts = np.array([[0.9, 0.3, 1.5], [0.9, 1.2, -0.2], [0.5, -2.0, 0.1], [1.1, 0.2, -0.05]])
+        m1, m2 = np.full(4, za), np.full(4, zb)
+        _, br = project_strict_aniso(pts, m1, m2)
+        assert (br == 2).all()
+        DP, d1, d2 = projection_jacobians(pts, br, m1, "strict", m2)
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = eps
+            num = (project_strict_aniso(pts + e, m1, m2)[0] - project_strict_aniso(pts - e, m1, m2)[0]) / (2 * eps)
+            np.testing.assert_allclose(DP[:, :, k], num, atol=2e-7)
+        # derivatives in mu: central for the nonzero coefficient, one-sided
+        # (mu >= 0) for the zero one
+        h = 1e-9
+
+        def dproj(d1, d2):
+            return (project_strict_aniso(pts, m1 + d1, m2 + d2)[0] - project_strict_aniso(pts, m1 - d1 * (za > 0),
+                                                                                      m2 - d2 * (zb > 0))[0])
+        num1 = dproj(h, 0.0) / (h * (1 + (za > 0)))
+        num2 = dproj(0.0, h) / (h * (1 + (zb > 0)))
+        np.testing.assert_allclose(d1, num1, atol=1e-6)
+        np.testing.assert_allclose(d2, num2, atol=1e-6)
     # circle: the disk operator's Jacobian, and dP/dmu1 + dP/dmu2 = dP/dmu of the disk
     ls = np.array([[0.7, 1.1, -0.4]])
     DPd, dmud, _ = projection_jacobians(ls, np.array([2]), np.array([0.5]))
@@ -248,3 +271,53 @@ def test_anisotropic_adjoint_matches_central_differences(seed):
                 assert abs(val - grad[name][m]) <= 1e-6 * (1 + abs(val)), (name, m, val, grad[name][m])
                 checked += 1
     assert checked >= 10
+
+
+def test_anisotropic_adjoint_zero_coefficient_one_sided():
+    """With one friction coefficient zero (the elliptic cone flattens to a
+    segment) the adjoint's gradient in that coefficient is the one-sided
+    derivative of the converged step (mu >= 0), the others central."""
+    p = scenes.random_problem(30, 14, 2, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+    mu, mu2 = np.array(p.mu, dtype=np.float64), np.array(p.mu, dtype=np.float64) * 0.6
+    mu[::3] = 0.0
+    mu2[1::3] = 0.0
+    p.mu, p.mu2 = mu, mu2
+    f = _fwd(p)
+    zero_slip = ((mu == 0) | (mu2 == 0)) & (f["branch"] == 2)
+    assert zero_slip.sum() >= 3
+    g = np.random.default_rng(21)
+    gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+    grad = adjoint(p, f, gv, gl)
+    dense = adjoint_dense(p, f, gv, gl)
+    for k in ("b", "phi", "mu", "mu2"):
+        np.testing.assert_allclose(grad[k], dense[k], rtol=0, atol=1e-9 * (1 + np.abs(dense[k]).max()))
+
+    def loss(**kw):
+        q = scenes.Problem(**{**p.__dict__, **kw})
+        fq = _fwd(q)
+        return gv @ fq["v"] + gl @ fq["lam"].ravel(), fq["branch"]
+
+    L0, _ = loss()
+    checked = 0
+    for m in np.nonzero(zero_slip)[0]:
+        for name in ("mu", "mu2"):
+            base = np.asarray(getattr(p, name))
+            e = np.zeros(p.n_contacts)
+            if base[m] == 0.0:
+                h = 1e-8
+                e[m] = h
+                Lp, br = loss(**{name: base + e})
+                if not np.array_equal(br, f["branch"]):
+                    continue
+                val = (Lp - L0) / h
+                assert abs(val - grad[name][m]) <= 1e-5 * (1 + abs(val)), (name, m, val, grad[name][m])
+            else:
+                h = 1e-6
+                e[m] = h
+                (Lp, bp), (Lm, bm) = loss(**{name: base + e}), loss(**{name: base - e})
+                if not (np.array_equal(bp, f["branch"]) and np.array_equal(bm, f["branch"])):
+                    continue
+                val = (Lp - Lm) / (2 * h)
+                assert abs(val - grad[name][m]) <= 1e-6 * (1 + abs(val)), (name, m, val, grad[name][m])
+            checked += 1
+    assert checked >= 4
