@@ -118,8 +118,7 @@ typedef struct {
                         friction on the elliptic cone lambda_n^2 >= t1^2/mu^2 + t2^2/mu2^2
                         (tangents = rows 1, 2 of R; Sec. III-E), solved by the strict
                         operator, which gives the maximal-dissipation impulse (Prop. 6).
-                        Not with VFPI_PROJ_PROXIMAL nor vfpi_step_backward
-                        (VFPI_E_UNSUPPORTED). */
+                        Not with VFPI_PROJ_PROXIMAL (VFPI_E_UNSUPPORTED). */
 } vfpi_contacts;
 
 typedef struct {
@@ -214,24 +213,31 @@ int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* env_node_off,
                       vfpi_stats* per_env_stats, hipStream_t stream);
 
 /* Adjoint of a converged vfpi_step (implicit differentiation through the
- * fixed point, with the strict projection's active branch per contact):
+ * fixed point, with the projection's active branch per contact):
  * given dL/dv and optionally dL/dlambda of the step's outputs, writes dL/db,
- * dL/dA (on A's pattern, NULL to skip), dL/dphi and dL/dmu.
- *   A, Jc     the same matrices as the forward call (FP64)
+ * dL/dA (on A's pattern, NULL to skip), dL/dphi, dL/dmu and (anisotropic
+ * friction) dL/dmu2.
+ *   A, Jc     the same matrices as the forward call (FP64), Jc->mu2 included
  *   tape      the buffer filled by the forward call
  *   grad_v    [n];  grad_lambda [3 n_c] or NULL (zero)
  *   grad_b    [n] out; grad_A_val [9 nnzb] out or NULL; grad_phi, grad_mu [n_c] out
+ *   grad_mu2  [n_c] out when Jc->mu2 != NULL (required then), else ignored.
+ *             The slip branch on the elliptic cone is differentiated
+ *             implicitly through the ellipse's closest-point condition; with
+ *             one coefficient zero (a segment) the derivative in that
+ *             coefficient is one-sided (mu >= 0).
  *   opts      max_iters / tol of the adjoint's own fixed-point iteration
  * The adjoint u solves u = g + (I - A W) G^T u with G = I - W J^T D_P Gamma^-1 J
  * (D_P = projection Jacobian of the last sweep), by transposed sweeps that
  * reuse the forward's layout; D-contacts, opts.omega and opts.projection
  * (both of which must equal the forward's) are supported.  Errors as
  * vfpi_step, plus VFPI_E_NO_TAPE for tape == NULL and VFPI_E_UNSUPPORTED for
- * mu2 (the elliptic projection is not differentiated). */
+ * mu2 with VFPI_PROJ_PROXIMAL (as in the forward). */
 int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc,
                        const void* tape, const double* grad_v, const double* grad_lambda,
                        double* grad_b, double* grad_A_val, double* grad_phi, double* grad_mu,
-                       const vfpi_opts* opts, vfpi_stats* stats, hipStream_t stream);
+                       double* grad_mu2, const vfpi_opts* opts, vfpi_stats* stats,
+                       hipStream_t stream);
 
 /* ---- virtual nodes (Sec. III-A, eq. vforce, eq. vnode) ------------------
  * A contact at a point that is not a node (a point of a triangle, of a rigid

@@ -97,7 +97,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                       P, P, ctypes.POINTER(vfpi_opts), P, P]
     lib.vfpi_step_batched.restype = ctypes.c_int
     lib.vfpi_step_backward.argtypes = [P, ctypes.POINTER(vfpi_bsr), ctypes.POINTER(vfpi_contacts), P, P, P, P, P,
-                                       P, P, ctypes.POINTER(vfpi_opts), P, P]
+                                       P, P, P, ctypes.POINTER(vfpi_opts), P, P]
     lib.vfpi_step_backward.restype = ctypes.c_int
     lib.vfpi_vnode_pattern.argtypes = [I32, P, P, I32, P, P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.vfpi_vnode_pattern.restype = ctypes.c_int
@@ -158,9 +158,9 @@ def vfpi_step_batched(ctx, n_env, env_node_off, env_con_off, env_order, A: vfpi_
 
 
 def vfpi_step_backward(ctx, A: vfpi_bsr, Jc: vfpi_contacts, tape, grad_v, grad_lambda, grad_b, grad_A_val,
-                       grad_phi, grad_mu, opts: vfpi_opts, stats, stream) -> int:
+                       grad_phi, grad_mu, grad_mu2, opts: vfpi_opts, stats, stream) -> int:
     return load().vfpi_step_backward(ctx, ctypes.byref(A), ctypes.byref(Jc), tape, grad_v, grad_lambda, grad_b,
-                                     grad_A_val, grad_phi, grad_mu, ctypes.byref(opts), stats, stream)
+                                     grad_A_val, grad_phi, grad_mu, grad_mu2, ctypes.byref(opts), stats, stream)
 
 
 def vfpi_vnode_pattern(n_o, row_ptr, col_idx, n_v, jv_ptr, jv_col, aug_row_ptr, aug_col_idx, cap) -> int:

@@ -3,7 +3,8 @@
 //
 // The step's fixed-point map (Sec. IV, Lemma 1 framing) is
 //   f(v) = v* + W J^T P(-Gamma^-1 (J v* + phi e1)),  v* = v - W (A v - b),
-// with P the strict or the proximal projection (eq. operator).  Holding W constant (the fixed
+// with P the strict or the proximal projection (eq. operator), or the strict
+// one on the elliptic cone (anisotropic friction).  Holding W constant (the fixed
 // point does not depend on it, consistency remark of Sec. III-B) and writing
 // D_P for P's Jacobian on the branch taken in the last sweep, G = I - W J^T D_P
 // Gamma^-1 J, the adjoint u of a loss with gradients (g_v, g_lam) solves
@@ -13,7 +14,7 @@
 // so every sweep is one product with A plus node-local work, like the forward
 // sweep.  Then, with r = J W u + g_lam and q = u - J^T Gamma^-1 D_P^T r:
 //     dL/db = W q,  dL/dA_ij = -(dL/db)_i v_j,  dL/dphi_m = -(D_P^T r)_n / gamma_m,
-//     dL/dmu_m = (dP/dmu)^T r_m.
+//     dL/dmu_m = (dP/dmu)^T r_m  (and dL/dmu2_m = (dP/dmu2)^T r_m).
 #include <math.h>
 
 #include "gridsync.h"
@@ -48,6 +49,7 @@ struct AdjArgs {
   double* grad_A;
   double* grad_phi;
   double* grad_mu;
+  double* grad_mu2;  // anisotropic friction only (else nullptr)
   int32_t max_iters, fixed;
   double tol;
   const int32_t* flags;
@@ -56,15 +58,81 @@ struct AdjArgs {
   int32_t proj;  // the forward's projection (VFPI_PROJ_*)
 };
 
-// y = D_P^T x for the contact's branch; *dmu = (dP/dmu)^T x.  Slip, strict
-// operator: dl_n/dn = 1, dl_t/dn = mu h, dl_t/dt = (mu n / s)(I - h h^T),
-// dl_t/dmu = n h with (n, t) = lambda*, s = |t|, h = t / s.  Slip, proximal
-// operator (projection onto the cone, P = a (1, mu h), a = (n + mu s) c,
-// c = 1 / (1 + mu^2)): the symmetric D_P = [c, mu c h^T; mu c h,
-// mu^2 c h h^T + (mu a / s)(I - h h^T)], dP_n/dmu = c (s - 2 mu a),
-// dP_t/dmu = (a + mu dP_n/dmu) h.
-VFPI_DEV void dp_transpose(const double* ls, int br, double mu, int proj, const double x[3], double y[3],
-                           double* dmu) {
+// Slip branch of the strict operator on the elliptic cone (mu1 != mu2):
+// lambda_n = n and x_i = A_i t_i / D_i, D_i = A_i + s, A_i = (mu_i n)^2, with s
+// the root of F(s) = sum_i A_i t_i^2 / D_i^2 - 1 (recomputed from lambda* by
+// the forward's own iteration).  Implicit differentiation, F_s = -2 sum_i
+// A_i t_i^2 / D_i^3: ds = -(sum_i 2 A_i t_i / D_i^2 dt_i + sum_i t_i^2 (s - A_i)
+// / D_i^3 dA_i) / F_s, dx_i = (t_i s / D_i^2) dA_i + (A_i / D_i) dt_i - (x_i /
+// D_i) ds, dA_i = 2 mu_i^2 n dn + 2 mu_i n^2 dmu_i.  With a zero coefficient
+// the ellipse is a segment and each tangent component is clamped on its own;
+// the zero coefficient's derivative is the one-sided one of the opening
+// ellipse (0 past the segment's tip; beside it dx_i = sign(t_i) n r dmu_i and
+// dx_j = -n t_j |t_i| / (b^2 r) dmu_i, r = sqrt(1 - t_j^2 / b^2), b = mu_j n).
+VFPI_DEV void dp_transpose_ellipse(const double* ls, double mu1, double mu2, const double x[3], double y[3],
+                                   double* dmu1, double* dmu2) {
+  const double n = ls[0], t[2] = {ls[1], ls[2]}, mu[2] = {mu1, mu2};
+  double dm[2] = {0.0, 0.0};
+  y[0] = x[0];
+  if (mu1 == 0.0 || mu2 == 0.0) {
+    for (int i = 0; i < 2; ++i) {
+      if (fabs(t[i]) > mu[i] * n) {
+        const double sg = t[i] > 0.0 ? 1.0 : -1.0;
+        y[0] += sg * mu[i] * x[1 + i];
+        y[1 + i] = 0.0;
+        dm[i] = sg * n * x[1 + i];
+      } else {
+        y[1 + i] = x[1 + i];
+      }
+    }
+    const int i = mu1 == 0.0 ? 0 : 1, j = 1 - i;
+    dm[i] = 0.0;
+    const double b = mu[j] * n;
+    if (b > 0.0 && fabs(t[j]) < b) {
+      const double q = t[j] / b, r = sqrt(1.0 - q * q);
+      dm[i] = (t[i] > 0.0 ? 1.0 : -1.0) * n * r * x[1 + i] - n * t[j] * fabs(t[i]) / (b * b * r) * x[1 + j];
+    }
+    *dmu1 = dm[0];
+    *dmu2 = dm[1];
+    return;
+  }
+  const double s = ellipse_multiplier(mu1 * n, mu2 * n, t[0], t[1]);
+  double A[2], D[2], P = 0.0, Fs = 0.0, gA_An = 0.0;
+  for (int i = 0; i < 2; ++i) {
+    A[i] = (mu[i] * n) * (mu[i] * n);
+    D[i] = A[i] + s;
+    const double iD = 1.0 / D[i];
+    P += A[i] * t[i] * iD * iD * x[1 + i];  // sum_i (x_i / D_i) z_i
+    Fs -= 2.0 * A[i] * t[i] * t[i] * iD * iD * iD;
+    gA_An += t[i] * t[i] * (s - A[i]) * iD * iD * iD * (2.0 * mu[i] * mu[i] * n);
+  }
+  const double ds_dn = -gA_An / Fs;
+  for (int i = 0; i < 2; ++i) {
+    const double iD = 1.0 / D[i];
+    const double An = 2.0 * mu[i] * mu[i] * n, Amu = 2.0 * mu[i] * n * n;
+    const double ds_dt = -2.0 * A[i] * t[i] * iD * iD / Fs;
+    const double ds_dmu = -t[i] * t[i] * (s - A[i]) * iD * iD * iD * Amu / Fs;
+    y[0] += t[i] * s * iD * iD * An * x[1 + i];
+    y[1 + i] = A[i] * iD * x[1 + i] - ds_dt * P;
+    dm[i] = t[i] * s * iD * iD * Amu * x[1 + i] - ds_dmu * P;
+  }
+  y[0] -= ds_dn * P;
+  *dmu1 = dm[0];
+  *dmu2 = dm[1];
+}
+
+// y = D_P^T x for the contact's branch; *dmu = (dP/dmu)^T x and *dmu2 =
+// (dP/dmu2)^T x (zero with isotropic friction).  R is the contact's packed
+// record (mu = R[10], mu2 = R[12]; mu2 != mu selects the elliptic cone, as in
+// the forward).  Slip, strict operator: dl_n/dn = 1, dl_t/dn = mu h,
+// dl_t/dt = (mu n / s)(I - h h^T), dl_t/dmu = n h with (n, t) = lambda*,
+// s = |t|, h = t / s.  Slip, proximal operator (projection onto the cone,
+// P = a (1, mu h), a = (n + mu s) c, c = 1 / (1 + mu^2)): the symmetric
+// D_P = [c, mu c h^T; mu c h, mu^2 c h h^T + (mu a / s)(I - h h^T)],
+// dP_n/dmu = c (s - 2 mu a), dP_t/dmu = (a + mu dP_n/dmu) h.
+VFPI_DEV void dp_transpose(const double* ls, int br, const double* R, int proj, const double x[3], double y[3],
+                           double* dmu, double* dmu2) {
+  *dmu2 = 0.0;
   if (br == BR_STICK) {
     y[0] = x[0];
     y[1] = x[1];
@@ -75,6 +143,11 @@ VFPI_DEV void dp_transpose(const double* ls, int br, double mu, int proj, const 
   if (br != BR_SLIP) {
     y[0] = y[1] = y[2] = 0.0;
     *dmu = 0.0;
+    return;
+  }
+  const double mu = R[10];
+  if (proj != VFPI_PROJ_PROXIMAL && R[12] != mu) {
+    dp_transpose_ellipse(ls, mu, R[12], x, y, dmu, dmu2);
     return;
   }
   const double n = ls[0], t1 = ls[1], t2 = ls[2];
@@ -109,9 +182,9 @@ VFPI_DEV void gt_node(const AdjArgs& a, int64_t i, int m, const double u[3], dou
   if (m < 0) return;
   const double* R = a.cpack + kPack * (int64_t)m;
   const double f = a.w[3 * i] / R[11];
-  double x[3], y[3], dmu;
+  double x[3], y[3], dmu, dmu2;
   for (int k = 0; k < 3; ++k) x[k] = (R[3 * k] * u[0] + R[3 * k + 1] * u[1] + R[3 * k + 2] * u[2]) * f;
-  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
+  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, x, y, &dmu, &dmu2);
   for (int r = 0; r < 3; ++r) out[r] -= R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
 }
 
@@ -121,11 +194,11 @@ VFPI_DEV void gt_pair(const AdjArgs& a, int m, bool first, const double ui[3], c
   const double* R = a.cpack + kPack * (int64_t)m;
   const int64_t i = a.cpair[2 * (int64_t)m], j = a.cpair[2 * (int64_t)m + 1];
   const double fi = a.w[3 * i] / R[11], fj = a.w[3 * j] / R[11];
-  double x[3], y[3], dmu;
+  double x[3], y[3], dmu, dmu2;
   for (int k = 0; k < 3; ++k)
     x[k] = (R[3 * k] * ui[0] + R[3 * k + 1] * ui[1] + R[3 * k + 2] * ui[2]) * fi -
            (R[3 * k] * uj[0] + R[3 * k + 1] * uj[1] + R[3 * k + 2] * uj[2]) * fj;
-  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
+  dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, x, y, &dmu, &dmu2);
   const double* u = first ? ui : uj;
   for (int r = 0; r < 3; ++r) {
     const double f = R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2];
@@ -162,8 +235,10 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
   if (flags != 0) {
     for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_nodes; k += (int64_t)G * blockDim.x)
       a.grad_b[k] = 0.0;
-    for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < a.n_contacts; k += (int64_t)G * blockDim.x)
+    for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < a.n_contacts; k += (int64_t)G * blockDim.x) {
       a.grad_phi[k] = a.grad_mu[k] = 0.0;
+      if (a.grad_mu2) a.grad_mu2[k] = 0.0;
+    }
     if (a.grad_A)
       for (int64_t k = b * (int64_t)blockDim.x + threadIdx.x; k < 9 * (int64_t)a.nnzb;
            k += (int64_t)G * blockDim.x)
@@ -193,8 +268,8 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
       double e[3] = {0.0, 0.0, 0.0};
       if (m >= 0) {
         const double* R = a.cpack + kPack * (int64_t)m;
-        double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
-        dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
+        double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu, dmu2;
+        dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, x, y, &dmu, &dmu2);
         const double gi = (adj_isd(a, m) && a.cpair[2 * (int64_t)m] != i) ? -1.0 / R[11] : 1.0 / R[11];
         for (int r = 0; r < 3; ++r) e[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
       }
@@ -305,7 +380,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
       const bool first = !isd || a.cpair[2 * (int64_t)m] == i;
       // r = J_m W u + g_lam (both nodes of a D-contact)
       const int64_t ni = isd ? a.cpair[2 * (int64_t)m] : i;
-      double ui[3], rr[3], y[3], dmu;
+      double ui[3], rr[3], y[3], dmu, dmu2;
       for (int r = 0; r < 3; ++r) ui[r] = ldv<true>(u_fin + 3 * ni + r);
       const double wi = a.w[3 * ni];
       for (int k = 0; k < 3; ++k) {
@@ -320,13 +395,14 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         for (int k = 0; k < 3; ++k)
           rr[k] -= R[3 * k] * (wj * uj[0]) + R[3 * k + 1] * (wj * uj[1]) + R[3 * k + 2] * (wj * uj[2]);
       }
-      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, rr, y, &dmu);
+      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, rr, y, &dmu, &dmu2);
       const double gi = 1.0 / R[11];
       const double sg = first ? gi : -gi;
       for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * sg;
       if (first) {
         a.grad_phi[m] = -y[0] * gi;
         a.grad_mu[m] = dmu;
+        if (a.grad_mu2) a.grad_mu2[m] = dmu2;
       }
     }
     double bb[3];
@@ -373,8 +449,10 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   if (flags != 0) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 3 * (int64_t)a.n_nodes; k += (int64_t)G * blockDim.x)
       a.grad_b[k] = 0.0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.n_contacts; k += (int64_t)G * blockDim.x)
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.n_contacts; k += (int64_t)G * blockDim.x) {
       a.grad_phi[k] = a.grad_mu[k] = 0.0;
+      if (a.grad_mu2) a.grad_mu2[k] = 0.0;
+    }
     if (a.grad_A)
       for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 9 * (int64_t)a.nnzb;
            k += (int64_t)G * blockDim.x)
@@ -451,8 +529,8 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   if (a.gl) {
     if (m >= 0) {
       const double* R = a.cpack + kPack * (int64_t)m;
-      double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu;
-      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, x, y, &dmu);
+      double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu, dmu2;
+      dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, x, y, &dmu, &dmu2);
       const double gi = 1.0 / R[11];
       for (int r = 0; r < 3; ++r) e3[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
     }
@@ -511,16 +589,17 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   if (m >= 0) {
     const double* R = a.cpack + kPack * (int64_t)m;
     const double wb = w3[0];
-    double rr[3], y[3], dmu;
+    double rr[3], y[3], dmu, dmu2;
     for (int k = 0; k < 3; ++k) {
       rr[k] = R[3 * k] * (wb * uu[0]) + R[3 * k + 1] * (wb * uu[1]) + R[3 * k + 2] * (wb * uu[2]);
       if (a.gl) rr[k] += a.gl[3 * (int64_t)m + k];
     }
-    dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R[10], a.proj, rr, y, &dmu);
+    dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, rr, y, &dmu, &dmu2);
     const double gi = 1.0 / R[11];
     for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
     a.grad_phi[m] = -y[0] * gi;
     a.grad_mu[m] = dmu;
+    if (a.grad_mu2) a.grad_mu2[m] = dmu2;
   }
   double bb[3];
   for (int r = 0; r < 3; ++r) {
@@ -548,8 +627,8 @@ using namespace vfpi;
 
 extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc, const void* tape,
                                   const double* grad_v, const double* grad_lambda, double* grad_b, double* grad_A_val,
-                                  double* grad_phi, double* grad_mu, const vfpi_opts* opts, vfpi_stats* stats,
-                                  hipStream_t stream) {
+                                  double* grad_phi, double* grad_mu, double* grad_mu2, const vfpi_opts* opts,
+                                  vfpi_stats* stats, hipStream_t stream) {
   if (!ctx || !A || !Jc || !grad_v || !grad_b || !opts || !stats) return VFPI_E_NULL;
   if (!tape) return VFPI_E_NO_TAPE;
   const int32_t N = A->n_nodes, nc = Jc->n_contacts;
@@ -559,7 +638,9 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
     return VFPI_E_NULL;
   if (N > ctx->max_nodes || A->nnzb > ctx->max_nnzb || nc > ctx->max_contacts) return VFPI_E_CAPACITY;
   if (opts->max_iters < 0 || !(opts->tol >= 0.0)) return VFPI_E_OPTS;
-  if (Jc->mu2) return VFPI_E_UNSUPPORTED;  // anisotropic friction: no projection Jacobian here
+  if (nc > 0 && Jc->mu2 && !grad_mu2) return VFPI_E_NULL;
+  if (opts->projection != VFPI_PROJ_STRICT && opts->projection != VFPI_PROJ_PROXIMAL) return VFPI_E_OPTS;
+  if (Jc->mu2 && opts->projection != VFPI_PROJ_STRICT) return VFPI_E_UNSUPPORTED;
   if (Jc->nnzb > 2 * (int64_t)nc) return VFPI_E_SHAPE;
   if (N == 0) {
     hipLaunchKernelGGL(k_stats_empty, dim3(1), dim3(1), 0, stream, stats);
@@ -577,7 +658,8 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (nc > 0)
     hipLaunchKernelGGL(k_contacts<double>, dim3((nc + 63) / 64), dim3(64), 0, stream, nc, Jc->nnzb, Jc->row_ptr,
                        Jc->col_idx, static_cast<const double*>(Jc->val), static_cast<const double*>(Jc->phi),
-                       static_cast<const double*>(Jc->mu), nullptr, N, ctx->cmap, cpack, ctx->cpair, ctx->flags,
+                       static_cast<const double*>(Jc->mu), static_cast<const double*>(Jc->mu2), N, ctx->cmap,
+                       cpack, ctx->cpair, ctx->flags,
                        1e-10);
   // W comes from the forward tape; the row pass rebuilds the interleaved copy of A.
   RowsArgs ra;
@@ -627,6 +709,7 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   aa.grad_A = grad_A_val;
   aa.grad_phi = grad_phi;
   aa.grad_mu = grad_mu;
+  aa.grad_mu2 = Jc->mu2 ? grad_mu2 : nullptr;
   aa.max_iters = opts->max_iters;
   aa.fixed = opts->fixed_iters;
   aa.tol = opts->tol;

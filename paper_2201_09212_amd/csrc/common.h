@@ -104,15 +104,34 @@ VFPI_DEV int project_proximal(T& n, T& t1, T& t2, T mu) {
   return BR_SLIP;
 }
 
+// Lagrange multiplier s > 0 of the closest point a_i^2 t_i / (a_i^2 + s) to
+// (t1, t2) outside the ellipse of semi-axes a, b > 0: the root of
+// F(s) = sum_i a_i^2 t_i^2 / (a_i^2 + s)^2 - 1, which is convex and falling
+// for s >= 0.  Each term of F + 1 is at most 1 at the root, so
+// s >= a |t1| - a^2 and s >= b |t2| - b^2: Newton starts at that lower bound
+// (left of the root) and climbs monotonically until it stops gaining.
+template <class T>
+VFPI_DEV T ellipse_multiplier(T a, T b, T t1, T t2) {
+  const T a2 = a * a, b2 = b * b, c1 = a2 * t1 * t1, c2 = b2 * t2 * t2;
+  T s = fmax(T(0), fmax(a * fabs(t1) - a2, b * fabs(t2) - b2));
+  for (int it = 0; it < 200; ++it) {
+    const T r1 = T(1) / (a2 + s), r2 = T(1) / (b2 + s);
+    const T f1 = c1 * r1 * r1, f2 = c2 * r2 * r2;
+    const T F = f1 + f2 - T(1);
+    const T dF = T(-2) * (f1 * r1 + f2 * r2);
+    const T sn = s - F / dF;
+    if (!(sn > s)) break;
+    s = sn;
+  }
+  return s;
+}
+
 // Strict operator on the elliptic cone t1^2/mu1^2 + t2^2/mu2^2 <= lambda_n^2
 // (anisotropic friction, Sec. III-E): lambda_t = the closest point to t in the
 // ellipse of semi-axes a = mu1 lambda_n, b = mu2 lambda_n, which is the
 // maximal-dissipation answer (Prop. 6).  Outside it, x_i = a_i^2 t_i / (a_i^2
-// + s) with s > 0 the root of F(s) = sum_i a_i^2 t_i^2 / (a_i^2 + s)^2 - 1.
-// F is convex and decreasing for s > -min(a^2, b^2) and F(0) > 0, so Newton
-// from any start left of the root climbs monotonically to it; it stops when a
-// step no longer increases s.  A zero semi-axis makes the ellipse a segment
-// (clamp).
+// + s) with s from ellipse_multiplier.  A zero semi-axis makes the ellipse a
+// segment (clamp).
 template <class T>
 VFPI_DEV int project_ellipse(T& n, T& t1, T& t2, T mu1, T mu2) {
   if (!(n > T(0))) {
@@ -129,20 +148,8 @@ VFPI_DEV int project_ellipse(T& n, T& t1, T& t2, T mu1, T mu2) {
   }
   const T tb = t1 * b, ta = t2 * a, ab = a * b;
   if (tb * tb + ta * ta <= ab * ab) return BR_STICK;
-  const T a2 = a * a, b2 = b * b, c1 = a2 * t1 * t1, c2 = b2 * t2 * t2;
-  // Each term of F + 1 is at most 1 at the root, so s >= a |t1| - a^2 and
-  // s >= b |t2| - b^2: Newton starts at that lower bound (still left of the
-  // root, so it still climbs monotonically) instead of at 0.
-  T s = fmax(T(0), fmax(a * fabs(t1) - a2, b * fabs(t2) - b2));
-  for (int it = 0; it < 200; ++it) {
-    const T r1 = T(1) / (a2 + s), r2 = T(1) / (b2 + s);
-    const T f1 = c1 * r1 * r1, f2 = c2 * r2 * r2;
-    const T F = f1 + f2 - T(1);
-    const T dF = T(-2) * (f1 * r1 + f2 * r2);
-    const T sn = s - F / dF;
-    if (!(sn > s)) break;
-    s = sn;
-  }
+  const T a2 = a * a, b2 = b * b;
+  const T s = ellipse_multiplier(a, b, t1, t2);
   t1 = a2 * t1 / (a2 + s);
   t2 = b2 * t2 / (b2 + s);
   return BR_SLIP;

@@ -182,13 +182,17 @@ class Solver:
         gA = torch.empty(9 * A.nnzb, dtype=torch.float64, device=dev) if want_A else None
         gphi = torch.empty(Jc.n_contacts, dtype=torch.float64, device=dev)
         gmu = torch.empty(Jc.n_contacts, dtype=torch.float64, device=dev)
+        gmu2 = torch.empty(Jc.n_contacts, dtype=torch.float64, device=dev) if Jc.mu2 is not None else None
         stats = new_stats(1, dev) if stats is None else stats
         o = make_opts(**opt)
         rc = _abi.vfpi_step_backward(self.ctx, A.desc(), Jc.desc(), _ptr(tape), _ptr(grad_v), _ptr(grad_lambda),
-                                     _ptr(gb), _ptr(gA), _ptr(gphi), _ptr(gmu), o, _ptr(stats),
+                                     _ptr(gb), _ptr(gA), _ptr(gphi), _ptr(gmu), _ptr(gmu2), o, _ptr(stats),
                                      stream_handle(stream))
         _abi.check(rc, "vfpi_step_backward")
-        return {"b": gb, "A": gA, "phi": gphi, "mu": gmu, "stats": stats}
+        out = {"b": gb, "A": gA, "phi": gphi, "mu": gmu, "stats": stats}
+        if gmu2 is not None:
+            out["mu2"] = gmu2
+        return out
 
 
 def vnode_augment(A_o: Bsr, b_o, v_o, jv_ptr, jv_col, jv_val, k_v, stream=None):

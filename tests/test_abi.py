@@ -53,7 +53,7 @@ def test_null_and_shape_errors_before_device_work():
     assert lib.vfpi_step_batched(None, 1, None, None, None, ctypes.byref(A), None, ctypes.byref(Jc), None, None,
                                  ctypes.byref(o), None, None) == _abi.VFPI_E_NULL
     assert lib.vfpi_step_backward(None, ctypes.byref(A), ctypes.byref(Jc), None, None, None, None, None, None,
-                                  None, ctypes.byref(o), None, None) == _abi.VFPI_E_NULL
+                                  None, None, ctypes.byref(o), None, None) == _abi.VFPI_E_NULL
     assert lib.vfpi_create(None, 1, 1, 1, 0) == _abi.VFPI_E_NULL
     h = ctypes.c_void_p()
     assert lib.vfpi_create(ctypes.byref(h), -1, 1, 1, 0) == _abi.VFPI_E_SHAPE

@@ -133,3 +133,109 @@ def test_adjoint_grid_and_single_workgroup_agree():
     say(f"  cloth64 adjoint: fwd {a['fwd_stats']['iters']} bwd {a['bwd_stats']['iters']} sweeps, {errs}")
     for k, e in errs.items():
         assert e <= 1e-6, (k, e)
+
+
+def _aniso_cases():
+    for name, p in list(_cases())[1:]:
+        p.mu2 = np.asarray(p.mu) * np.random.default_rng(p.n_nodes).uniform(0.3, 1.8, size=p.n_contacts)
+        yield name, p
+    p = scenes.random_problem(120, 50, 6, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), n_d_contacts=15,
+                              tag="adj")
+    p.mu2 = np.asarray(p.mu) * np.random.default_rng(7).uniform(0.3, 1.8, size=p.n_contacts)
+    yield "random120_d", p
+    # zero coefficients: the ellipse degenerates to a segment (componentwise clamp)
+    p = scenes.random_problem(200, 90, 2, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+    mu, mu2 = np.array(p.mu, dtype=np.float64), np.array(p.mu, dtype=np.float64) * 0.6
+    mu[::5] = 0.0
+    mu2[2::5] = 0.0
+    p.mu, p.mu2 = mu, mu2
+    yield "random200_zero", p
+
+
+@pytest.mark.parametrize("variant", [0, 1, 3])
+def test_aniso_adjoint_matches_oracle(variant):
+    """Anisotropic friction (strict operator on the elliptic cone): the
+    adjoint's b, A, phi, mu and mu2 gradients against the oracle's, on
+    S-contacts, D-contacts and with zero coefficients (segments)."""
+    for name, p in _aniso_cases():
+        g = np.random.default_rng(8)
+        gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+        out = gpu_fwd_bwd(p, gv, gl, variant=variant)
+        fwd = oracle.vfpi(p, max_iters=200000, tol=1e-14)
+        ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
+        assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
+        assert out["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, out["bwd_stats"]
+        errs = {k: rel(out[k], ref[k]) for k in ("b", "A", "phi", "mu", "mu2")}
+        slip = int((fwd["branch"] == 2).sum())
+        say(f"  {name} aniso variant {variant}: {slip} slipping, bwd {out['bwd_stats']['iters']} sweeps, {errs}")
+        assert slip >= 3
+        for k, e in errs.items():
+            assert e <= 1e-7, (name, k, e)
+
+
+def test_aniso_adjoint_vs_central_differences_of_gpu_forward():
+    """b, phi, mu and mu2 gradients with anisotropic friction against central
+    differences of the HIP forward."""
+    p = scenes.random_problem(40, 18, 5, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+    p.mu2 = np.asarray(p.mu) * np.random.default_rng(9).uniform(0.3, 1.8, size=p.n_contacts)
+    g = np.random.default_rng(4)
+    gv = g.normal(size=p.n)
+    out = gpu_fwd_bwd(p, gv)
+    s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
+
+    def loss(q):
+        A, Jc, b, v = upload(q)
+        lam, st = s.step(A, b, Jc, v, max_iters=200000, tol=1e-14)
+        torch.cuda.synchronize()
+        return float(gv @ v.cpu().numpy())
+
+    eps = 1e-6
+    checked = 0
+    for k in g.choice(p.n, 6, replace=False):
+        e = np.zeros(p.n)
+        e[k] = eps
+        fd = (loss(scenes.Problem(**{**p.__dict__, "b": p.b + e})) - loss(scenes.Problem(**{**p.__dict__, "b": p.b - e}))) / (2 * eps)
+        assert abs(fd - out["b"][k]) <= 1e-4 * max(1.0, abs(fd)), (k, fd, out["b"][k])
+        checked += 1
+    for m in range(p.n_contacts):
+        for name in ("phi", "mu", "mu2"):
+            e = np.zeros(p.n_contacts)
+            e[m] = eps
+            base = np.asarray(getattr(p, name))
+            fd = (loss(scenes.Problem(**{**p.__dict__, name: base + e})) -
+                  loss(scenes.Problem(**{**p.__dict__, name: base - e}))) / (2 * eps)
+            assert abs(fd - out[name][m]) <= 1e-4 * max(1.0, abs(fd)), (name, m, fd, out[name][m])
+            checked += 1
+    say(f"  central differences checked (aniso): {checked}")
+
+
+def test_autograd_solve_with_aniso_friction():
+    """vfpi_solve (torch.autograd.Function over the HIP forward and adjoint)
+    hands b, phi, mu and mu2 gradients to PyTorch: they equal the oracle's."""
+    from paper_2201_09212_amd.autograd import vfpi_solve
+    p = scenes.random_problem(70, 40, 1, degree=4.0, phi_scale=0.4, mu_range=(0.2, 0.9), tag="adj")
+    p.mu2 = np.asarray(p.mu) * np.random.default_rng(11).uniform(0.3, 1.8, size=p.n_contacts)
+    crp, ccol, cval = p.jc_bsr()
+    assert np.array_equal(np.diff(crp), np.ones(p.n_contacts))  # S-contacts: one block per row
+    dev = torch.device("cuda", 0)
+    t = {k: torch.tensor(np.asarray(getattr(p, k), dtype=np.float64), device=dev, requires_grad=True)
+         for k in ("b", "phi", "mu", "mu2")}
+    A_val = torch.tensor(p.val, device=dev).view(-1, 3, 3).requires_grad_(True)
+    s = vf.Solver(p.n_nodes, p.nnzb, p.n_contacts)
+    g = np.random.default_rng(12)
+    gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+    v, lam, st = vfpi_solve(s, A_val, t["b"], t["phi"], t["mu"], torch.as_tensor(p.v0, device=dev),
+                            torch.as_tensor(p.row_ptr, device=dev, dtype=torch.int32),
+                            torch.as_tensor(p.col_idx, device=dev, dtype=torch.int32), p.n_nodes,
+                            torch.as_tensor(ccol, device=dev, dtype=torch.int32),
+                            torch.as_tensor(cval, device=dev).view(-1, 3, 3), mu2=t["mu2"],
+                            fwd_opts=dict(max_iters=200000, tol=1e-14), bwd_opts=dict(max_iters=200000, tol=1e-13))
+    L = (torch.as_tensor(gv, device=dev) * v).sum() + (torch.as_tensor(gl, device=dev) * lam).sum()
+    L.backward()
+    fwd = oracle.vfpi(p, max_iters=200000, tol=1e-14)
+    ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
+    errs = {k: rel(t[k].grad.cpu().numpy(), ref[k]) for k in ("b", "phi", "mu", "mu2")}
+    errs["A"] = rel(A_val.grad.cpu().numpy().ravel(), ref["A"].ravel())
+    say(f"  autograd aniso: {errs}")
+    for k, e in errs.items():
+        assert e <= 1e-7, (k, e)

@@ -105,7 +105,7 @@ def test_aniso_unsupported_combinations():
     tape = s.tape(p.n_nodes, p.n_contacts)
     s.step(A, b, Jc, v, max_iters=50, tape=tape)
     with pytest.raises(vf.VfpiError, match="not supported"):
-        s.step_backward(A, Jc, tape, torch.zeros(p.n, dtype=torch.float64, device="cuda"))
+        s.step_backward(A, Jc, tape, torch.zeros(p.n, dtype=torch.float64, device="cuda"), projection="proximal")
     bad = p.mu2.copy()
     bad[3] = -0.1
     Jc.mu2 = torch.as_tensor(bad, device="cuda")
