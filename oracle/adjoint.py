@@ -63,7 +63,7 @@ def ellipse_jacobian(n, t, mu1, mu2):
     DP = np.zeros((3, 3))
     dmu = np.zeros((2, 3))
     DP[0, 0] = 1.0
-    if mu1 == 0.0 or mu2 == 0.0:
+    if mu1 * n == 0.0 or mu2 * n == 0.0:   # a zero semi-axis, as the projection tests it
         # a zero semi-axis: the ellipse is a segment and P clamps each tangent
         # component to [-mu_i n, mu_i n] on its own
         for i in range(2):
@@ -78,7 +78,7 @@ def ellipse_jacobian(n, t, mu1, mu2):
         # closest point stays at the tip to first order; beside the segment
         # s = a |t_i| / r + O(a^2), r = sqrt(1 - t_j^2 / b^2), so
         # dx_i/dmu_i = sign(t_i) n r and dx_j/dmu_i = -n t_j |t_i| / (b^2 r).
-        i = 0 if mu1 == 0.0 else 1
+        i = 0 if mu1 * n == 0.0 else 1
         j = 1 - i
         dmu[i] = 0.0
         b = mu[j] * n

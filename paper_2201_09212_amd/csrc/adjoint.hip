@@ -74,7 +74,7 @@ VFPI_DEV void dp_transpose_ellipse(const double* ls, double mu1, double mu2, con
   const double n = ls[0], t[2] = {ls[1], ls[2]}, mu[2] = {mu1, mu2};
   double dm[2] = {0.0, 0.0};
   y[0] = x[0];
-  if (mu1 == 0.0 || mu2 == 0.0) {
+  if (mu1 * n == 0.0 || mu2 * n == 0.0) {  // the forward's test for a segment
     for (int i = 0; i < 2; ++i) {
       if (fabs(t[i]) > mu[i] * n) {
         const double sg = t[i] > 0.0 ? 1.0 : -1.0;
@@ -85,7 +85,7 @@ VFPI_DEV void dp_transpose_ellipse(const double* ls, double mu1, double mu2, con
         y[1 + i] = x[1 + i];
       }
     }
-    const int i = mu1 == 0.0 ? 0 : 1, j = 1 - i;
+    const int i = mu1 * n == 0.0 ? 0 : 1, j = 1 - i;
     dm[i] = 0.0;
     const double b = mu[j] * n;
     if (b > 0.0 && fabs(t[j]) < b) {
