@@ -223,6 +223,7 @@ VFPI_DEV void arow_bsr(const AdjArgs& a, const double* y, int64_t x, double out[
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
   __shared__ double s_red[NW];
+  __shared__ double s_poll[3 * NW];  // see grid_sum
   int seq = 0;
   const int G = gridDim.x;
   const int b = blockIdx.x;
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         stv<true>(a.S[1] + 3 * i + r, a.w[3 * i + r] * e[r]);
       }
     });
-    grid_barrier(a.slots, G, lb, ++seq, s_red);
+    grid_barrier(a.slots, G, lb, ++seq, s_poll);
   }
   // phase B: g~ = g_v - e + A p; u0 = g~, t0 = G^T u0, s0 = W t0
   for_my_nodes([&](int64_t n0, int cnt) {
@@ -315,7 +316,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
       stv<true>(a.S[0] + 3 * i + r, a.w[3 * i + r] * t[r]);
     }
   });
-  grid_barrier(a.slots, G, lb, ++seq, s_red);
+  grid_barrier(a.slots, G, lb, ++seq, s_poll);
   int cur = 0;
   if (a.max_iters > 0) {
     int l = 0;
@@ -356,7 +357,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
         }
       });
       th2 = block_sum(th2, s_red);
-      const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+      const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_poll);
       cur = nxt;
       if (stop) break;
     }
@@ -434,6 +435,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
 template <int NW, int KC>
 __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   __shared__ double s_red[NW];
+  __shared__ double s_poll[3 * NW];  // see grid_sum
   __shared__ double s_out[NW][192];
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
@@ -536,7 +538,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     }
     const double p3[3] = {w3[0] * e3[0], w3[1] * e3[1], w3[2] * e3[2]};
     publish(a.S[1], p3);
-    grid_barrier(a.slots, G, lb, ++seq, s_red);
+    grid_barrier(a.slots, G, lb, ++seq, s_poll);
   }
   // phase B: g~ = g_v - e + A p; u0 = g~, t0 = G^T u0, s0 = W t0
   double gt[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0}, tt[3] = {0.0, 0.0, 0.0};
@@ -550,7 +552,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     }
     const double s3[3] = {w3[0] * tt[0], w3[1] * tt[1], w3[2] * tt[2]};
     publish(a.S[0], s3);
-    grid_barrier(a.slots, G, lb, ++seq, s_red);
+    grid_barrier(a.slots, G, lb, ++seq, s_poll);
   }
   int cur = 0;
   if (a.max_iters > 0) {
@@ -573,7 +575,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       const double s3[3] = {w3[0] * tt[0], w3[1] * tt[1], w3[2] * tt[2]};
       publish(a.S[nxt], s3);
       th2 = block_sum(th2, s_red);
-      const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+      const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_poll);
       cur = nxt;
       if (stop) break;
     }

@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
   constexpr bool COH = true;
   __shared__ double s_vs[2][TPN == 3 ? NW : 1][3][64];
   __shared__ double s_red[TPN * NW];
+  __shared__ double s_poll[3 * TPN * NW];  // see grid_sum
   __shared__ int s_ired[3 * TPN * NW];
 
   const int G = gridDim.x;
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
     th2 = block_sum(th2, s_red);
     double theta;
     const bool stop =
-        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red, &theta);
+        grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_poll, &theta);
     double* t = vcur;
     vcur = vnext;
     vnext = t;
@@ -193,6 +194,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
   constexpr bool COH = true;
   constexpr int U = (64 * NW >= 960) ? 2 : 4;
   __shared__ double s_red[NW];
+  __shared__ double s_poll[3 * NW];  // see grid_sum
   __shared__ int s_ired[3 * NW];
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
       }
     }
     if (l >= 2) {
-      grid_sum3(a.slots + kBBSlotOffset, G, lb, l - 1, dots, s_red);
+      grid_sum3(a.slots + kBBSlotOffset, G, lb, l - 1, dots, s_red, s_poll);
       if (!a.bb2 && dots[0] > 0.0 && dots[1] > 0.0) alpha = dots[0] / dots[1];
       else if (a.bb2 && dots[1] > 0.0 && dots[2] > 0.0) alpha = dots[1] / dots[2];
     }
@@ -304,7 +306,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
       }
     }
     th2 = block_sum(th2, s_red);
-    const bool stop = grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_red);
+    const bool stop = grid_residual_step(a.slots, G, lb, l, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_poll);
     double* t = vcur;
     vcur = vnext;
     vnext = t;
@@ -353,6 +355,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   // VGPRs (beyond them the compiler parks A in AGPRs and copies it back every
   // sweep).  CH: Chebyshev acceleration (keeps v^{l-1} in registers).
   __shared__ double s_red[NW];
+  __shared__ double s_poll[3 * NW];  // see grid_sum
   __shared__ int s_ired[3 * NW];
   __shared__ double s_out[NW][192];
   __shared__ double s_bw[NW][6][64];      // b (3), W (3)
@@ -413,6 +416,12 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       s_cl[slot][k][lane] = d.scol[q + pos];
 #pragma unroll
       for (int e = 0; e < 9; ++e) s_al[slot][k][e][lane] = d.sval[9 * q + (int64_t)e * ck + pos];
+    } else {
+      // a zero block on a valid column: the sweep's LDS levels then run
+      // without branches (adding the exact zero leaves A v unchanged)
+      s_cl[slot][k][lane] = act ? (int)i : 0;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) s_al[slot][k][e][lane] = 0.0;
     }
     off += ck;
   }
@@ -467,14 +476,15 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
       }
     }
-    // LDS levels, two at a time (both gathers in flight before the products)
+    // LDS levels, two at a time (both gathers in flight before the products);
+    // levels a row lacks hold zero blocks, so there is no branch here
 #pragma unroll
     for (int k0 = 0; k0 < KL; k0 += 2) {
       double xl[2][3];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int k = k0 + u;
-        if (k < KL && KC + k < nk) {
+        if (k < KL) {
           const double* xp = vcur + 3 * (int64_t)s_cl[slot][k][lane];
           xl[u][0] = ldv<COH>(xp);
           xl[u][1] = ldv<COH>(xp + 1);
@@ -484,11 +494,15 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int k = k0 + u;
-        if (k < KL && KC + k < nk) {
+        if (k < KL) {
+          // all nine LDS reads of the block issue before its products
+          double al[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) al[e] = s_al[slot][k][e][lane];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int r = 0; r < 3; ++r)
-            Av[r] += s_al[slot][k][3 * r][lane] * xl[u][0] + s_al[slot][k][3 * r + 1][lane] * xl[u][1] +
-                     s_al[slot][k][3 * r + 2][lane] * xl[u][2];
+            Av[r] += al[3 * r] * xl[u][0] + al[3 * r + 1] * xl[u][1] + al[3 * r + 2] * xl[u][2];
         }
       }
     }
@@ -506,7 +520,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
             dots[2] += z * z;
           }
         }
-        grid_sum3(a.slots + kBBSlotOffset, G, lb, l - 1, dots, s_red);
+        grid_sum3(a.slots + kBBSlotOffset, G, lb, l - 1, dots, s_red, s_poll);
         if (!a.bb2 && dots[0] > 0.0 && dots[1] > 0.0) alpha = dots[0] / dots[1];
         else if (a.bb2 && dots[1] > 0.0 && dots[2] > 0.0) alpha = dots[1] / dots[2];
       }
@@ -534,7 +548,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) stv<COH>(a.avbuf + 3 * i + r, vs[r]);
       }
-      grid_barrier(a.slots, G, lb, 2 * l - 1, s_red);
+      grid_barrier(a.slots, G, lb, 2 * l - 1, s_poll);
       if (act && isd) {
         ContactRec<double> cr;
 #pragma unroll
@@ -603,7 +617,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     th2 = block_sum(th2, s_red);
     double theta;
     const bool stop = grid_residual_step(a.slots, G, lb, has_d ? 2 * l : l, th2, l, a.max_iters, a.fixed, a.tol,
-                                         a.stats, s_red, &theta);
+                                         a.stats, s_poll, &theta);
     double* t = vcur;
     vcur = vnext;
     vnext = t;

@@ -46,10 +46,27 @@ VFPI_DEV uint64_t tagged(double x, unsigned tag) {
 }
 VFPI_DEV double untag(uint64_t b) { return __builtin_bit_cast(double, b & ~0xffull); }
 
+// Sum over the workgroup of the polled slots with one workgroup barrier:
+// wave sums (DPP) go to red[0, nw) and every thread adds them in wave order,
+// the same arithmetic as block_sum.  No trailing barrier is needed: red is
+// written again only by the next grid_sum / grid_sum3, after its own
+// pre-publication barrier, which every thread reaches after reading here.
+VFPI_DEV double poll_sum(double acc, double* red) {
+  acc = wave_sum(acc);
+  const int nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
 // Synchronization number `seq` (1, 2, ... in the same order in every
 // workgroup).  `x` is this workgroup's partial (valid in thread 0).  Returns
-// the fixed-order sum of all workgroups' partials in every thread.
-VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, double* s_red) {
+// the fixed-order sum of all workgroups' partials in every thread.  s_poll
+// (LDS, 3 doubles per wave, apart from the callers' block_sum buffer) takes
+// the wave sums of the polled slots.
+VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, double* s_poll) {
   const unsigned tag = sync_tag(seq);
   uint64_t* sl = slots + (seq & 1) * (int64_t)kMaxGridSlots * kSlotPad;
   drain();
@@ -61,14 +78,14 @@ VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, doub
     while (((b = ld_relaxed(sl + (int64_t)k * kSlotPad)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
     acc += untag(b);
   }
-  return block_sum(acc, s_red);
+  return poll_sum(acc, s_poll);
 }
 
 // Three partials at once (valid in every thread of the workgroup), in the slot
 // region `reg` = [2][3][kMaxGridSlots] with its own sequence numbers; the
 // same tagging and double-buffering argument as grid_sum applies per region.
 // Returns the fixed-order sums in x, in every thread.
-VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], double* s_red) {
+VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], double* s_red, double* s_poll) {
   if (G == 1) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) x[q] = block_sum(x[q], s_red);
@@ -93,8 +110,21 @@ VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], doub
       acc[q] += untag(b);
     }
   }
+  const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) x[q] = block_sum(acc[q], s_red);
+  for (int q = 0; q < 3; ++q) acc[q] = wave_sum(acc[q]);
+  double* red = s_poll;  // 3 nw doubles, one barrier for the three sums (see poll_sum)
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) red[q * nw + (threadIdx.x >> 6)] = acc[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[q * nw + i];
+    x[q] = t;
+  }
 }
 
 // Residual reduction + convergence test of Alg. 1 (theta < tol or l = l_max).
@@ -102,8 +132,9 @@ VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], doub
 // workgroup's partial (valid in thread 0).  Workgroup 0 writes iters,
 // status and theta of the stopping sweep.
 VFPI_DEV bool grid_residual_step(uint64_t* slots, int G, int lb, int seq, double th2, int l, int max_iters,
-                                 int fixed, double tol, vfpi_stats* stats, double* s_red, double* theta_out = nullptr) {
-  const double tot = (G == 1) ? th2 : grid_sum(slots, G, lb, seq, th2, s_red);
+                                 int fixed, double tol, vfpi_stats* stats, double* s_poll,
+                                 double* theta_out = nullptr) {
+  const double tot = (G == 1) ? th2 : grid_sum(slots, G, lb, seq, th2, s_poll);
   const double theta = sqrt(tot);
   if (theta_out) *theta_out = theta;
   const bool conv = !fixed && theta < tol;
@@ -118,12 +149,12 @@ VFPI_DEV bool grid_residual_step(uint64_t* slots, int G, int lb, int seq, double
 
 // Plain grid barrier: every write before it is visible to every workgroup
 // after it (through coherent loads).
-VFPI_DEV void grid_barrier(uint64_t* slots, int G, int lb, int seq, double* s_red) {
+VFPI_DEV void grid_barrier(uint64_t* slots, int G, int lb, int seq, double* s_poll) {
   if (G == 1) {
     __syncthreads();
     return;
   }
-  (void)grid_sum(slots, G, lb, seq, 0.0, s_red);
+  (void)grid_sum(slots, G, lb, seq, 0.0, s_poll);
 }
 
 // Branch counts of the final sweep: integer atomics, so the totals do not
