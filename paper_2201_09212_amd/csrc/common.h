@@ -198,7 +198,12 @@ VFPI_DEV bool level_group(int k0, int nk, int64_t& off, uint64_t m[U], int cnt[U
 // indices and block entries of the group are loaded first, then all gathers
 // of x, then the products, so the group's memory latencies overlap instead of
 // chaining level by level.  The accumulation order is level by level.
-template <class T, bool COH = false, int U = 4>
+//
+// BF (default for FP64, whose kernels are latency-bound): the group's loads
+// are issued by every lane as one straight-line block.  The FP32 batched
+// kernel is bandwidth-bound and keeps the form where only lanes with the
+// level load.
+template <class T, bool COH = false, int U = 4, bool BF = (sizeof(T) == 8)>
 VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restrict__ sval,
                               const T* __restrict__ x, int64_t base, int nk, int lane, int k_start,
                               int64_t off_start, T acc[3]) {
@@ -208,36 +213,76 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
     int cnt[U];
     int64_t offk[U];
     if (!level_group<U>(k0, nk, off, m, cnt, offk)) break;
-    int c[U];
-    T a[U][9];
+    if constexpr (BF) {
+      // Every lane loads, so that the group's loads form one straight-line
+      // block: behind a divergent branch each level's gather would wait for all
+      // earlier loads (the wait counters are merged at the branch's join).  A
+      // lane without level k0 + u reads a block inside that level's range (or
+      // level k0's, when no lane has k0 + u) and drops it in the select below.
+      int c[U];
+      T a[U][9];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      c[u] = 0;
-      if (k0 + u < nk) {
-        const int pos = lanes_below(m[u], lane);
-        const int64_t q = base + offk[u];
+      for (int u = 0; u < U; ++u) {
+        const bool any = cnt[u] > 0;  // the same in every lane; cnt[0] > 0
+        const int cu = any ? cnt[u] : cnt[0];
+        const int64_t q = base + (any ? offk[u] : offk[0]);
+        const int pos = min(lanes_below(any ? m[u] : m[0], lane), cu - 1);
         c[u] = scol[q + pos];
         const T* ap = sval + 9 * q + pos;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cnt[u]];
+        for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cu];
       }
-    }
-    T xs[U][3];
+      T xs[U][3];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (k0 + u < nk) {
+      for (int u = 0; u < U; ++u) {
         const T* xp = x + 3 * (int64_t)c[u];
         xs[u][0] = ldv<COH>(xp);
         xs[u][1] = ldv<COH>(xp + 1);
         xs[u][2] = ldv<COH>(xp + 2);
       }
-    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (k0 + u < nk) {
-        acc[0] += a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2];
-        acc[1] += a[u][3] * xs[u][0] + a[u][4] * xs[u][1] + a[u][5] * xs[u][2];
-        acc[2] += a[u][6] * xs[u][0] + a[u][7] * xs[u][1] + a[u][8] * xs[u][2];
+      for (int u = 0; u < U; ++u) {
+        const bool has = k0 + u < nk;
+        const T y0 = acc[0] + (a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2]);
+        const T y1 = acc[1] + (a[u][3] * xs[u][0] + a[u][4] * xs[u][1] + a[u][5] * xs[u][2]);
+        const T y2 = acc[2] + (a[u][6] * xs[u][0] + a[u][7] * xs[u][1] + a[u][8] * xs[u][2]);
+        acc[0] = has ? y0 : acc[0];
+        acc[1] = has ? y1 : acc[1];
+        acc[2] = has ? y2 : acc[2];
+      }
+    } else {
+      // streaming form (bandwidth-bound callers): only lanes with the level load
+      int c[U];
+      T a[U][9];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        c[u] = 0;
+        if (k0 + u < nk) {
+          const int pos = lanes_below(m[u], lane);
+          const int64_t q = base + offk[u];
+          c[u] = scol[q + pos];
+          const T* ap = sval + 9 * q + pos;
+#pragma unroll
+          for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cnt[u]];
+        }
+      }
+      T xs[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u < nk) {
+          const T* xp = x + 3 * (int64_t)c[u];
+          xs[u][0] = ldv<COH>(xp);
+          xs[u][1] = ldv<COH>(xp + 1);
+          xs[u][2] = ldv<COH>(xp + 2);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u < nk) {
+          acc[0] += a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2];
+          acc[1] += a[u][3] * xs[u][0] + a[u][4] * xs[u][1] + a[u][5] * xs[u][2];
+          acc[2] += a[u][6] * xs[u][0] + a[u][7] * xs[u][1] + a[u][8] * xs[u][2];
+        }
       }
     }
   }
