@@ -303,8 +303,9 @@ def batched_bench(args, torch, vf, scenes):
 
 def adjoint_bench(args, torch, vf, scenes):
     """64x64 cloth: one converged step (tol 1e-13) forward with tape and its
-    adjoint (kernel times), and a 100-step rollout with gradient (checkpoint
-    every 10 steps) against the same rollout without gradient."""
+    adjoint (kernel times), also with anisotropic friction and with the
+    proximal operator, and a 100-step rollout with gradient (checkpoint every
+    10 steps) against the same rollout without gradient."""
     from paper_2201_09212_amd.autograd import rollout
     from scenes.cloth_torch import TorchCloth
     dev = torch.device("cuda", 0)
@@ -333,6 +334,25 @@ def adjoint_bench(args, torch, vf, scenes):
         g = s.step_backward(A, Jc, tape, gv, max_iters=100000, tol=1e-13, want_A=True)
         bwd.append(vf.vfpi_timing_read(s.ctx)[1])
         fit, bit = vf.read_stats(st)[0]["iters"], vf.read_stats(g["stats"])[0]["iters"]
+
+    def variant_step(Jc_, **opt):
+        """The same landed step with another contact model: kernel times and
+        sweep counts of the converged forward and of its adjoint."""
+        fw, bw = [], []
+        for _ in range(3):
+            v = torch.as_tensor(p.v0, device=dev).clone()
+            _, st_ = s.step(A, b, Jc_, v, tape=tape, max_iters=100000, tol=1e-13, **opt)
+            fw.append(vf.vfpi_timing_read(s.ctx)[1])
+            g_ = s.step_backward(A, Jc_, tape, gv, max_iters=100000, tol=1e-13, want_A=True, **opt)
+            bw.append(vf.vfpi_timing_read(s.ctx)[1])
+        f_, b_ = vf.read_stats(st_)[0], vf.read_stats(g_["stats"])[0]
+        return {"step_fwd_ms": sorted(fw)[1], "step_bwd_ms": sorted(bw)[1], "fwd_sweeps": f_["iters"],
+                "bwd_sweeps": b_["iters"], "n_slip": f_["n_slip"],
+                "converged": bool(f_["status"] == 0 and b_["status"] == 0)}
+
+    Jc_aniso = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, device=dev, mu2=0.5 * np.asarray(p.mu))
+    variants = {"anisotropic, mu2 = mu/2 (f4)": variant_step(Jc_aniso),
+                "proximal operator (f3)": variant_step(Jc, projection="proximal")}
     vf.vfpi_timing_enable(s.ctx, False)
     # rollout
     x0t = torch.as_tensor(x0, device=dev)
@@ -365,7 +385,7 @@ def adjoint_bench(args, torch, vf, scenes):
             "step_fwd_ms": fm, "step_bwd_ms": bm, "bwd_over_fwd_step": bm / fm, "fwd_sweeps": fit,
             "bwd_sweeps": bit, "n_contacts": p.n_contacts, "rollout_steps": steps,
             "rollout_fwd_s": t_fwd, "rollout_fwd_bwd_s": t_fb,
-            "bwd_over_fwd_rollout": (t_fb - t_fwd) / t_fwd,
+            "bwd_over_fwd_rollout": (t_fb - t_fwd) / t_fwd, "contact_models": variants,
             "workload": "cloth64x64 on plane, FP64, converged to 1e-13, checkpoint every 10 steps"}
 
 
