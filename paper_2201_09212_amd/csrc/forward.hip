@@ -396,7 +396,11 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   for (int k = 0; k < KC; ++k) {
     const uint64_t m = ballot(k < nk);
     const int ck = __popcll(m);
+    // a level the row lacks: a zero block on column 0, so the sweep's
+    // register levels run without branches (adding the exact zero)
     col[k] = 0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) av[k][e] = 0.0;
     if (k < nk) {
       const int pos = lanes_below(m, lane);
       const int64_t q = base + off;
@@ -460,21 +464,17 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     double xs[KC][3];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      if (k < nk) {
-        const double* xp = vcur + 3 * (int64_t)col[k];
-        xs[k][0] = ldv<COH>(xp);
-        xs[k][1] = ldv<COH>(xp + 1);
-        xs[k][2] = ldv<COH>(xp + 2);
-      }
+      const double* xp = vcur + 3 * (int64_t)col[k];
+      xs[k][0] = ldv<COH>(xp);
+      xs[k][1] = ldv<COH>(xp + 1);
+      xs[k][2] = ldv<COH>(xp + 2);
     }
     double Av[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      if (k < nk) {
-        Av[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
-        Av[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
-        Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
-      }
+      Av[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
+      Av[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
+      Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
     }
     // LDS levels, two at a time (both gathers in flight before the products);
     // levels a row lacks hold zero blocks, so there is no branch here
