@@ -476,7 +476,10 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   for (int k = 0; k < KC; ++k) {
     const uint64_t mk = ballot(k < nk);
     const int ck = __popcll(mk);
+    // a level the row lacks: a zero block on column 0 (no branch in spmv)
     col[k] = 0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) av[k][e] = 0.0;
     if (k < nk) {
       const int pos = lanes_below(mk, lane);
       const int64_t q = base + off;
@@ -496,21 +499,17 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     double xs[KC][3];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      if (k < nk) {
-        const double* xp = x + 3 * (int64_t)col[k];
-        xs[k][0] = ldv<true>(xp);
-        xs[k][1] = ldv<true>(xp + 1);
-        xs[k][2] = ldv<true>(xp + 2);
-      }
+      const double* xp = x + 3 * (int64_t)col[k];
+      xs[k][0] = ldv<true>(xp);
+      xs[k][1] = ldv<true>(xp + 1);
+      xs[k][2] = ldv<true>(xp + 2);
     }
     out[0] = out[1] = out[2] = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      if (k < nk) {
-        out[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
-        out[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
-        out[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
-      }
+      out[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
+      out[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
+      out[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
     }
     spmv_rows3_from<double, true, (NW >= 8 ? 2 : 1)>(a.scol, a.sval, x, base, nk, lane, KC, off_tail, out);
   };
