@@ -7,10 +7,15 @@ registers for the whole step (one chunk pass per workgroup); ``slots`` = 64-node
 ``cap`` = workgroup limit (0 = library default).  The tuner times each
 candidate on the caller's own problem with the library's HIP events (a short
 fixed number of sweeps), keeps the fastest, and caches the choice in a JSON
-file keyed by the problem's shape so later runs skip the search.
+file keyed by the problem's shape, the candidate list and a hash of the built
+library, so later runs of the same build skip the search and a rebuilt
+library searches again.  The cache lives in the user's cache directory
+(``$XDG_CACHE_HOME/vfpi`` or ``~/.cache/vfpi``), or at ``$VFPI_TUNE_CACHE``.
 """
 from __future__ import annotations
 
+import functools
+import hashlib
 import json
 import os
 import zlib
@@ -19,8 +24,25 @@ import torch
 
 from . import _abi
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-CACHE = os.environ.get("VFPI_TUNE_CACHE", os.path.join(HERE, "tuned_variants.json"))
+
+
+def cache_path():
+    env = os.environ.get("VFPI_TUNE_CACHE")
+    if env:
+        return env
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "vfpi", "tuned_variants.json")
+
+
+@functools.lru_cache(maxsize=None)
+def library_hash(path=_abi.LIB_PATH):
+    """Short content hash of the built library: tuned choices are only valid
+    for the kernels they were timed with."""
+    h = hashlib.sha256()
+    with open(path, "rb") as f:
+        for blk in iter(lambda: f.read(1 << 20), b""):
+            h.update(blk)
+    return h.hexdigest()[:12]
 
 PLAIN_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 2 | (1 << 8), 2 | (2 << 8),
                     1 | (2 << 8) | (128 << 16), 1 | (4 << 8) | (128 << 16), 3 | (16 << 8), 3 | (4 << 8),
@@ -31,18 +53,20 @@ BATCHED_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 1 | (8 << 8), 2 
 
 def _load():
     try:
-        with open(CACHE) as f:
+        with open(cache_path()) as f:
             return json.load(f)
     except (OSError, ValueError):
         return {}
 
 
 def _store(cache):
+    path = cache_path()
     try:
-        tmp = CACHE + ".tmp"
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = f"{path}.{os.getpid()}.tmp"
         with open(tmp, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
-        os.replace(tmp, CACHE)
+        os.replace(tmp, path)
     except OSError:
         pass
 
@@ -61,8 +85,12 @@ def _time(solver, call, reps=3):
         _abi.vfpi_timing_enable(solver.ctx, False)
 
 
+def cache_key(key, candidates):
+    return f"{key}/cand{zlib.crc32(repr(candidates).encode()) & 0xffff:04x}/lib{library_hash()}"
+
+
 def _search(key, candidates, call_for, log):
-    key = f"{key}/cand{zlib.crc32(repr(candidates).encode()) & 0xffff:04x}"
+    key = cache_key(key, candidates)
     cache = _load()
     if key in cache:
         return int(cache[key]["variant"])

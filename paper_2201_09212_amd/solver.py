@@ -3,8 +3,11 @@ out.  PyTorch provides memory and streams only; every step of the solve runs
 in the HIP library."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import dataclasses
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -117,22 +120,48 @@ def stream_handle(stream=None):
     return s.cuda_stream
 
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Release every context still open when the program ends, while the HIP
+    runtime, torch and any profiler attached to the process are still alive
+    (atexit handlers run before the interpreter tears modules down)."""
+    for s in list(_LIVE):
+        s.close()
+
+
 class Solver:
     """Owns one library context (device workspace for problems up to the
-    given sizes)."""
+    given sizes).  Release it with ``close()`` (or a ``with`` block); a
+    context still open at exit is released by an atexit handler.  The
+    finalizer frees it too, except during interpreter shutdown, when no HIP
+    call is made (the process's memory goes with it)."""
 
     def __init__(self, max_nodes, max_nnzb, max_contacts, max_envs=0, device=None):
+        self.ctx = None
         self.device = _dev(device)
         with torch.cuda.device(self.device):
             self.ctx = _abi.vfpi_create(int(max_nodes), int(max_nnzb), int(max_contacts), int(max_envs))
         self.capacity = (max_nodes, max_nnzb, max_contacts, max_envs)
+        _LIVE.add(self)
 
     def close(self):
         if self.ctx:
-            _abi.vfpi_destroy(self.ctx)
-            self.ctx = None
+            ctx, self.ctx = self.ctx, None
+            _LIVE.discard(self)
+            _abi.vfpi_destroy(ctx)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
+        if sys.is_finalizing() or not getattr(self, "ctx", None):
+            return
         try:
             self.close()
         except Exception:

@@ -10,7 +10,7 @@ import paper_2201_09212_amd as vf
 import scenes
 from oracle.adjoint import adjoint as oracle_adjoint
 from paper_2201_09212_amd import _abi
-from tests.gpu_util import rel, say, upload
+from tests.gpu_util import gate, say, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -52,10 +52,8 @@ def test_adjoint_matches_oracle(name, p, with_glam, variant):
     ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
     assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
     assert out["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, out["bwd_stats"]
-    errs = {k: rel(out[k], ref[k]) for k in ("b", "A", "phi", "mu")}
+    errs = {k: gate(out[k], ref[k], 1e-7, f"{name} grad {k}") for k in ("b", "A", "phi", "mu")}
     say(f"  {name} glam={with_glam}: fwd {out['fwd_stats']['iters']} bwd {out['bwd_stats']['iters']} sweeps, {errs}")
-    for k, e in errs.items():
-        assert e <= 1e-7, (k, e)
 
 
 @pytest.mark.parametrize("opt", [{}, {"projection": "proximal"}, {"projection": "proximal", "omega": 0.05}])
@@ -72,11 +70,9 @@ def test_proximal_adjoint_matches_oracle(variant, opt):
         ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
         assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
         assert out["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, out["bwd_stats"]
-        errs = {k: rel(out[k], ref[k]) for k in ("b", "A", "phi", "mu")}
+        errs = {k: gate(out[k], ref[k], 1e-7, f"{name} grad {k}") for k in ("b", "A", "phi", "mu")}
         slip = int((fwd["branch"] == 2).sum())
         say(f"  {name} {opt} variant {variant}: {slip} slipping, bwd {out['bwd_stats']['iters']} sweeps, {errs}")
-        for k, e in errs.items():
-            assert e <= 1e-7, (k, e)
 
 
 @pytest.mark.parametrize("opt", [{}, {"projection": "proximal"}])
@@ -126,13 +122,11 @@ def test_adjoint_grid_and_single_workgroup_agree():
         say(f"  adjoint variant {var:#x}: {b['bwd_stats']['iters']} sweeps (default {a['bwd_stats']['iters']})")
         assert abs(b["bwd_stats"]["iters"] - a["bwd_stats"]["iters"]) <= 1
         for k in ("b", "A", "phi", "mu"):
-            assert rel(a[k], b[k]) <= 1e-10, (var, k)
+            gate(a[k], b[k], 1e-10, f"variant {var:#x} grad {k}")
     fwd = oracle.vfpi(p, max_iters=200000, tol=1e-13)
     ref = oracle_adjoint(p, fwd, gv, tol=1e-14)
-    errs = {k: rel(a[k], ref[k]) for k in ("b", "A", "phi", "mu")}
+    errs = {k: gate(a[k], ref[k], 1e-6, f"cloth64 grad {k}") for k in ("b", "A", "phi", "mu")}
     say(f"  cloth64 adjoint: fwd {a['fwd_stats']['iters']} bwd {a['bwd_stats']['iters']} sweeps, {errs}")
-    for k, e in errs.items():
-        assert e <= 1e-6, (k, e)
 
 
 def _aniso_cases():
@@ -165,12 +159,10 @@ def test_aniso_adjoint_matches_oracle(variant):
         ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
         assert out["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
         assert out["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, out["bwd_stats"]
-        errs = {k: rel(out[k], ref[k]) for k in ("b", "A", "phi", "mu", "mu2")}
+        errs = {k: gate(out[k], ref[k], 1e-7, f"{name} aniso grad {k}") for k in ("b", "A", "phi", "mu", "mu2")}
         slip = int((fwd["branch"] == 2).sum())
         say(f"  {name} aniso variant {variant}: {slip} slipping, bwd {out['bwd_stats']['iters']} sweeps, {errs}")
         assert slip >= 3
-        for k, e in errs.items():
-            assert e <= 1e-7, (name, k, e)
 
 
 def test_aniso_adjoint_vs_central_differences_of_gpu_forward():
@@ -234,8 +226,6 @@ def test_autograd_solve_with_aniso_friction():
     L.backward()
     fwd = oracle.vfpi(p, max_iters=200000, tol=1e-14)
     ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
-    errs = {k: rel(t[k].grad.cpu().numpy(), ref[k]) for k in ("b", "phi", "mu", "mu2")}
-    errs["A"] = rel(A_val.grad.cpu().numpy().ravel(), ref["A"].ravel())
+    errs = {k: gate(t[k].grad.cpu().numpy(), ref[k], 1e-7, f"autograd grad {k}") for k in ("b", "phi", "mu", "mu2")}
+    errs["A"] = gate(A_val.grad.cpu().numpy().ravel(), ref["A"].ravel(), 1e-7, "autograd grad A")
     say(f"  autograd aniso: {errs}")
-    for k, e in errs.items():
-        assert e <= 1e-7, (k, e)

@@ -1,5 +1,5 @@
 """Batched FP32 HIP path (FP64 residual) vs the FP64 oracle per environment:
-bar 1e-4 relative on v and lambda at a fixed sweep count, for every kernel
+bar 1e-4 relative, element by element, on v and lambda at a fixed sweep count, for every kernel
 variant, work-queue order and a sample of the full 2048-environment batch."""
 import numpy as np
 import pytest
@@ -9,7 +9,7 @@ import oracle
 import paper_2201_09212_amd as vf
 import scenes
 from paper_2201_09212_amd import _abi
-from tests.gpu_util import rel, say
+from tests.gpu_util import gate, say
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -57,11 +57,10 @@ def _check_envs(batch, v, lam, stats, L, envs_idx=None, **okw):
         ref = oracle.vfpi(pe, max_iters=L, fixed_iters=True, **okw)
         n0, n1 = batch.env_node_off[e], batch.env_node_off[e + 1]
         m0, m1 = batch.env_con_off[e], batch.env_con_off[e + 1]
-        ev = rel(v[3 * n0:3 * n1], ref["v"])
-        el = rel(lam[3 * m0:3 * m1], ref["lam"]) if m1 > m0 else 0.0
-        worst = max(worst, ev, el)
         assert stats[e]["iters"] == L and stats[e]["status"] == _abi.VFPI_S_MAXITER, (e, stats[e])
-        assert ev <= TOL and el <= TOL, (e, pe.n_nodes, pe.n_contacts, ev, el)
+        ev = gate(v[3 * n0:3 * n1], ref["v"], TOL, f"env {e} (N={pe.n_nodes}) v")
+        el = gate(lam[3 * m0:3 * m1], ref["lam"], TOL, f"env {e} (nc={pe.n_contacts}) lambda")
+        worst = max(worst, ev, el)
     return worst
 
 
@@ -94,7 +93,7 @@ def test_batched_per_env_convergence():
         ref = oracle.vfpi(pe, max_iters=5000, tol=3e-5)
         assert st[e]["status"] == _abi.VFPI_S_CONVERGED and st[e]["theta"] < 3e-5, (e, st[e])
         n0, n1 = batch.env_node_off[e], batch.env_node_off[e + 1]
-        assert rel(v[3 * n0:3 * n1], ref["v"]) <= 1e-3, e
+        gate(v[3 * n0:3 * n1], ref["v"], 1e-3, f"env {e} converged v")
     iters = [s["iters"] for s in st]
     say(f"  per-env sweeps: min {min(iters)} max {max(iters)}")
     assert len(set(iters)) > 1  # environments stop on their own residual

@@ -7,7 +7,7 @@ import pytest
 import scenes
 from oracle.chebyshev import vfpi_chebyshev
 from paper_2201_09212_amd import _abi
-from tests.gpu_util import gpu_step, rel, say
+from tests.gpu_util import fixed_parity, gate, gpu_step, say
 from tests.test_gpu_batched import run_batched
 
 pytestmark = pytest.mark.gpu
@@ -31,11 +31,9 @@ def test_chebyshev_fixed_sweeps_parity(variant, ls, u):
             continue
         L = 40
         ref = vfpi_chebyshev(p, max_iters=L, fixed_iters=True, l_s=ls, u=u)
-        v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, variant=VARIANTS[variant], cheby_ls=ls,
-                                 cheby_u=u)
-        ev, el = rel(v, ref["v"]), rel(lam, ref["lam"])
-        say(f"  {name} {variant} ls={ls} u={u}: rel_v={ev:.2e} rel_lam={el:.2e}")
-        assert st["iters"] == L and ev <= 1e-9 and el <= 1e-9
+        ev, el, st, ties = fixed_parity(p, ref, L, 1e-9, f"{name} {variant}", variant=VARIANTS[variant],
+                                        cheby_ls=ls, cheby_u=u)
+        say(f"  {name} {variant} ls={ls} u={u}: rel_v={ev:.2e} rel_lam={el:.2e} branch ties={ties}")
 
 
 def test_chebyshev_converged_fewer_sweeps():
@@ -46,7 +44,7 @@ def test_chebyshev_converged_fewer_sweeps():
     plain = gpu_step(p, max_iters=5000, tol=1e-8)[2]
     say(f"  cloth128 to 1e-8: plain {plain['iters']} sweeps, Chebyshev {st['iters']} (oracle {ref['iters']})")
     assert st["status"] == _abi.VFPI_S_CONVERGED and abs(st["iters"] - ref["iters"]) <= 1
-    assert rel(vv, ref["v"]) <= 1e-7
+    gate(vv, ref["v"], 1e-7, "cloth128 Chebyshev converged v")
     assert st["iters"] < plain["iters"]
 
 
@@ -60,6 +58,5 @@ def test_batched_chebyshev_parity():
         ref = vfpi_chebyshev(pe, max_iters=L, fixed_iters=True, l_s=4, u=0.9)
         n0, n1 = batch.env_node_off[e], batch.env_node_off[e + 1]
         m0, m1 = batch.env_con_off[e], batch.env_con_off[e + 1]
-        assert rel(v[3 * n0:3 * n1], ref["v"]) <= 1e-4, e
-        if m1 > m0:
-            assert rel(lam[3 * m0:3 * m1], ref["lam"]) <= 1e-4, e
+        gate(v[3 * n0:3 * n1], ref["v"], 1e-4, f"env {e} v")
+        gate(lam[3 * m0:3 * m1], ref["lam"], 1e-4, f"env {e} lambda")

@@ -1,5 +1,5 @@
 """A seeded sweep over problem shapes and options on the HIP path vs the FP64
-oracle at a fixed sweep count (bar 1e-9): node counts from 1 to a few
+oracle at a fixed sweep count (bar 1e-9 element by element, branches per contact): node counts from 1 to a few
 thousand (ragged last chunks), row lengths from 2 to ~40 blocks, S- and
 D-contacts, both projections, omega, anisotropic friction, Chebyshev and BB
 step sizes, and every launch kind, including workgroup caps."""
@@ -9,7 +9,7 @@ import pytest
 import oracle
 import scenes
 from oracle.chebyshev import vfpi_chebyshev
-from tests.gpu_util import gpu_step, rel, say
+from tests.gpu_util import fixed_parity, say
 
 pytestmark = pytest.mark.gpu
 
@@ -55,10 +55,9 @@ def test_seeded_config_parity(k):
                              omega=opt.get("omega", 0.0), projection=opt.get("projection", "strict"))
     else:
         ref = oracle.vfpi(p, max_iters=L, fixed_iters=True, **{a: b for a, b in opt.items()})
-    v, lam, st, _ = gpu_step(p, max_iters=L, fixed_iters=True, variant=kind, **opt)
-    ev, el = rel(v, ref["v"]), rel(lam, ref["lam"])
+    o = dict(opt)
+    proj = o.pop("projection", "strict")
+    ev, el, st, ties = fixed_parity(p, ref, L, 1e-9, f"cfg {k}", projection=proj, variant=kind, **o)
     say(f"  cfg {k}: N={p.n_nodes} nc={p.n_contacts} D={int((p.c_node_j >= 0).sum())} "
         f"max row {int(np.diff(p.row_ptr).max()) if p.n_nodes else 0} variant={kind:#x} opt={opt} "
-        f"aniso={p.mu2 is not None}: rel_v={ev:.2e} rel_lam={el:.2e}")
-    assert st["iters"] == L and st["status"] == 1, st
-    assert ev <= 1e-9 and el <= 1e-9
+        f"aniso={p.mu2 is not None}: rel_v={ev:.2e} rel_lam={el:.2e} branch ties={ties}")
