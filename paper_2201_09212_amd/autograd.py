@@ -115,7 +115,8 @@ class VfpiStepFn(torch.autograd.Function):
         else:
             guard.add(stats)
         if record is not None:
-            record.append((stats, tape[16 * 3 * n_nodes + 24 * nc:].view(torch.int32).clone()))
+            off = 48 * n_nodes + 24 * nc  # tape layout: w, v (3N doubles each), lambda* (3 n_c), branch (n_c)
+            record.append((stats, tape[off:off + 4 * nc].view(torch.int32).clone()))
         ctx.solver = solver
         ctx.A = A
         ctx.Jc = Jc

@@ -98,8 +98,9 @@ class ClothScene:
             K9[p, _slot(dr, dc)] -= kb
             K9[q, _slot(-dr, -dc)] -= kb
             fs = -self.k * (ln - rest)[:, None] * d
-            np.add.at(f, p, fs)
-            np.add.at(f, q, -fs)
+            # p (and q) are distinct within one spring direction
+            f[p] += fs
+            f[q] -= fs
         A9 = (self.h * self.h) * K9
         A9[:, 4] += self.mass * np.eye(3)
         val = A9[self.exists]
@@ -171,6 +172,54 @@ def cloth_cfg2(seed: int = 0):
         cap = np.where(rho <= r1, np.sqrt(np.maximum(r * r - rho * rho, 0.0)), z1 - slope * (rho - r1))
         z = np.maximum(z, cap)
     x[:, 2] = np.maximum(z, -0.3) + gap
+    v = g.normal(0.0, 0.02, size=(s * s, 3))
+    v[:, 2] -= np.where(z < 0.0, 0.1, 0.0)
+    return sc, x, v
+
+
+def cloth_drape(side: int, seed: int = 0):
+    """A side x side cloth draped over fixed spheres, for the size sweep: the
+    cloth128 recipe (r ~ U[5,15] cm, centres at z = 0, non-overlapping in xy,
+    per-node mu ~ U[0.2, 0.8], cap plus a gap in [-0.5, 1] mm out to 0.92 r,
+    then the tangent fall-off, hanging parts clipped at -0.3 m and falling at
+    0.1 m/s) with the sphere count scaled with the area, 16 per 128 x 128.
+    Each sphere only shapes the nodes its cap and fall-off reach.  Returns
+    (scene, x, v)."""
+    s = int(side)
+    g = rng("cloth_drape", seed, f"side{s}")
+    half = (s - 1) / 2 * 0.01
+    n_sph = max(1, int(round(16 * (s / 128.0) ** 2)))
+    centers, radii = [], []
+    tries = 0
+    while len(centers) < n_sph and tries < 200 * n_sph:
+        tries += 1
+        r = g.uniform(0.05, min(0.15, half - 0.01))
+        c = g.uniform(-half + r, half - r, size=2)
+        if all(np.hypot(*(c - c2)) > r + r2 + 0.01 for c2, r2 in zip(centers, radii)):
+            centers.append(c)
+            radii.append(r)
+    obstacles = [("sphere", (c[0], c[1], 0.0), r) for c, r in zip(centers, radii)]
+    mu = g.uniform(0.2, 0.8, size=s * s)
+    sc = ClothScene(side=s, obstacles=obstacles, mu_node=mu)
+    x = sc.rest_positions(0.0)
+    gap = g.uniform(-5e-4, 1e-3, size=s * s)
+    z = np.full((s, s), -0.3)
+    xs = x[:, 0].reshape(s, s)
+    ys = x[:, 1].reshape(s, s)
+    for c, r in zip(centers, radii):
+        r1 = 0.92 * r
+        z1 = np.sqrt(r * r - r1 * r1)
+        slope = r1 / z1
+        reach = r1 + (z1 + 0.3) / slope
+        c0 = max(0, int(np.floor((c[0] - reach + half) / 0.01)))
+        c1 = min(s, int(np.ceil((c[0] + reach + half) / 0.01)) + 1)
+        r0 = max(0, int(np.floor((c[1] - reach + half) / 0.01)))
+        r1i = min(s, int(np.ceil((c[1] + reach + half) / 0.01)) + 1)
+        rho = np.hypot(xs[r0:r1i, c0:c1] - c[0], ys[r0:r1i, c0:c1] - c[1])
+        cap = np.where(rho <= r1, np.sqrt(np.maximum(r * r - rho * rho, 0.0)), z1 - slope * (rho - r1))
+        z[r0:r1i, c0:c1] = np.maximum(z[r0:r1i, c0:c1], cap)
+    z = z.ravel()
+    x[:, 2] = z + gap
     v = g.normal(0.0, 0.02, size=(s * s, 3))
     v[:, 2] -= np.where(z < 0.0, 0.1, 0.0)
     return sc, x, v

@@ -173,3 +173,12 @@ def fem_ctx(seed: int = 0):
     """Paper-size block: 16 x 16 x 4 cells (1,445 nodes, 4,335 DOF), same
     material and obstacles scaled down (2 spheres)."""
     return _fem_snapshot((16, 16, 4), 2, 0.02, 0.04, 0.025, seed, "fem16x16x4")
+
+
+def fem_block(cells, seed: int = 0):
+    """FEM block of any size for the size sweep: the FEM-block recipe (same
+    material, h, margin and obstacle sizes) with the sphere count scaled with
+    the footprint, 8 per 64 x 64 cells (at least 2)."""
+    cx, cy, cz = (int(c) for c in cells)
+    n_sph = max(2, int(round(8 * cx * cy / (64.0 * 64.0))))
+    return _fem_snapshot((cx, cy, cz), n_sph, 0.02, 0.06, 0.025, seed, f"fem{cx}x{cy}x{cz}")
