@@ -239,6 +239,31 @@ int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc
                        double* grad_mu2, const vfpi_opts* opts, vfpi_stats* stats,
                        hipStream_t stream);
 
+/* ---- the plain solve without allocation --------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * vfpi_step_noalloc runs exactly vfpi_step's kernels (same results, bit for
+ * bit, for the same inputs and options) but needs no context: its workspace
+ * lies in one device array of VFPI_NOALLOC_SCRATCH_BYTES inside the library,
+ * one copy per GPU, held from the first call on that GPU until the process
+ * ends.  The call allocates and frees nothing.  The caller still passes every
+ * input and output (device pointers, as for vfpi_step); the workspace takes
+ *   76 nnzb + 316 N + 112 n_c + 573,952 bytes
+ * (each of its 14 parts rounded up to 256 bytes), which must fit the array:
+ * about 33,000 nodes of a cloth with 9 blocks per row.  Every call on one GPU
+ * shares that GPU's array, and each call starts by clearing the parts that
+ * must start at zero; two calls that overlap on one GPU (on different
+ * streams, or from different threads) race and give undefined results.
+ * Calls must be ordered, e.g. on one stream.  The workspace is used on the
+ * current device.  opts->reuse_w is refused (another call may have
+ * overwritten the row sums).  The timing aid does not apply.
+ * Errors: as vfpi_step; VFPI_E_CAPACITY when the workspace does not fit;
+ * VFPI_E_OPTS for reuse_w. */
+#define VFPI_NOALLOC_SCRATCH_BYTES (32u << 20)
+int vfpi_step_noalloc(const vfpi_bsr* A, const double* b, const vfpi_contacts* Jc, double* v,
+                      double* lambda, const vfpi_opts* opts, vfpi_stats* stats, void* tape,
+                      hipStream_t stream);
+
 /* ---- virtual nodes (Sec. III-A, eq. vforce, eq. vnode) ------------------
  * A contact at a point that is not a node (a point of a triangle, of a rigid
  * body) gets a temporary virtual node q tied to the point's velocity J_v v_o

@@ -40,7 +40,9 @@ VFPI_PROJ_PROXIMAL = 1
 
 ENTRY_POINTS = ("vfpi_create", "vfpi_destroy", "vfpi_tape_bytes", "vfpi_step", "vfpi_step_batched",
                 "vfpi_step_backward", "vfpi_vnode_pattern", "vfpi_vnode_values", "vfpi_timing_enable",
-                "vfpi_timing_read", "vfpi_error_string")
+                "vfpi_timing_read", "vfpi_error_string", "vfpi_step_noalloc")
+
+VFPI_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class vfpi_bsr(ctypes.Structure):
@@ -93,6 +95,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vfpi_step.argtypes = [P, ctypes.POINTER(vfpi_bsr), P, ctypes.POINTER(vfpi_contacts), P, P,
                               ctypes.POINTER(vfpi_opts), P, P, P]
     lib.vfpi_step.restype = ctypes.c_int
+    lib.vfpi_step_noalloc.argtypes = [ctypes.POINTER(vfpi_bsr), P, ctypes.POINTER(vfpi_contacts), P, P,
+                                      ctypes.POINTER(vfpi_opts), P, P, P]
+    lib.vfpi_step_noalloc.restype = ctypes.c_int
     lib.vfpi_step_batched.argtypes = [P, I32, P, P, P, ctypes.POINTER(vfpi_bsr), P, ctypes.POINTER(vfpi_contacts),
                                       P, P, ctypes.POINTER(vfpi_opts), P, P]
     lib.vfpi_step_batched.restype = ctypes.c_int
@@ -149,6 +154,11 @@ def vfpi_error_string(code: int) -> str:
 def vfpi_step(ctx, A: vfpi_bsr, b, Jc: vfpi_contacts, v, lam, opts: vfpi_opts, stats, tape, stream) -> int:
     return load().vfpi_step(ctx, ctypes.byref(A), b, ctypes.byref(Jc), v, lam, ctypes.byref(opts), stats, tape,
                             stream)
+
+
+def vfpi_step_noalloc(A: vfpi_bsr, b, Jc: vfpi_contacts, v, lam, opts: vfpi_opts, stats, tape, stream) -> int:
+    return load().vfpi_step_noalloc(ctypes.byref(A), b, ctypes.byref(Jc), v, lam, ctypes.byref(opts), stats, tape,
+                                    stream)
 
 
 def vfpi_step_batched(ctx, n_env, env_node_off, env_con_off, env_order, A: vfpi_bsr, b, Jc: vfpi_contacts, v, lam,

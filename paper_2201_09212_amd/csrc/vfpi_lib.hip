@@ -5,3 +5,4 @@
 #include "batched.hip"
 #include "adjoint.hip"
 #include "vnode.hip"
+#include "noalloc.hip"
