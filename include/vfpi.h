@@ -132,15 +132,18 @@ typedef struct {
   int32_t reuse_w;       /* 1: keep the row sums a_dd, ||A_d*||^2 of the previous
                             call on this context (W reuse across steps, Sec. IV-C) */
   int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16
-                            | LDS levels << 24.
+                            | LDS levels << 24 | load group << 26.
                             vfpi_step kinds: 1 grid, lane per node; 2 grid, lane per row;
                             3, 4 the same in one workgroup; 5 grid, the node's first
                             block levels of A in registers and the next ones in LDS
                             (LDS levels: 0 when rows average more than 9 blocks, 1 off,
                             2 on; refused with VFPI_E_OPTS when the grid needs more
-                            than one workgroup per CU).  0 = library
+                            than one workgroup per CU).  Load group (kind 1 with 8
+                            chunk slots): levels of A loaded together, 1 two, else
+                            four.  0 = library
                             default: kind 5 with the fewest chunk slots (2, 4, 5, 6, 8)
-                            that fit, else kind 1 (also with BB step sizes).
+                            that fit, else kind 1 with 8 slots and groups of two
+                            levels (also with BB step sizes, which take 4 slots).
                             vfpi_step_backward: 0 or 5 register-resident (S-contacts),
                             1 streaming, 3 one workgroup.  Batched kinds: see below. */
   int32_t cheby_ls;      /* 0: off; l_s >= 1: Chebyshev acceleration (Alg. 3):

@@ -219,18 +219,25 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
       // earlier loads (the wait counters are merged at the branch's join).  A
       // lane without level k0 + u reads a block inside that level's range (or
       // level k0's, when no lane has k0 + u) and drops it in the select below.
-      int c[U];
+      // The group's column indices are issued before its block entries, so
+      // that each gather waits only for the columns (loads return in issue
+      // order) while the entries are still in flight.
+      int c[U], cu[U], pos[U];
+      int64_t q[U];
       T a[U][9];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool any = cnt[u] > 0;  // the same in every lane; cnt[0] > 0
-        const int cu = any ? cnt[u] : cnt[0];
-        const int64_t q = base + (any ? offk[u] : offk[0]);
-        const int pos = min(lanes_below(any ? m[u] : m[0], lane), cu - 1);
-        c[u] = scol[q + pos];
-        const T* ap = sval + 9 * q + pos;
+        cu[u] = any ? cnt[u] : cnt[0];
+        q[u] = base + (any ? offk[u] : offk[0]);
+        pos[u] = min(lanes_below(any ? m[u] : m[0], lane), cu[u] - 1);
+        c[u] = scol[q[u] + pos[u]];
+      }
 #pragma unroll
-        for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cu];
+      for (int u = 0; u < U; ++u) {
+        const T* ap = sval + 9 * q[u] + pos[u];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cu[u]];
       }
       T xs[U][3];
 #pragma unroll

@@ -96,7 +96,7 @@ struct GridArgs {
 // the workgroups meet once per sweep in the residual reduction.  A workgroup
 // keeps the same nodes in every sweep, and the iterate moves between
 // workgroups through coherent loads / stores only (see gridsync.h).
-template <int TPN, int NW>
+template <int TPN, int NW, int U = (TPN == 3 ? (64 * TPN * NW >= 960 ? 4 : 8) : (64 * TPN * NW >= 960 ? 2 : 4))>
 __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
   constexpr bool COH = true;
   __shared__ double s_vs[2][TPN == 3 ? NW : 1][3][64];
@@ -144,10 +144,10 @@ __global__ void __launch_bounds__(64 * TPN * NW) k_vfpi_grid(GridArgs a) {
       const int64_t n0 = c * 64;
       const int cnt = (c < c1) ? (int)min<int64_t>(64, a.n_nodes - n0) : 0;
       if (TPN == 3)
-        sweep_chunk_row<double, COH, (64 * TPN * NW >= 960 ? 4 : 8)>(d, vcur, vnext, n0, cnt, lane, r,
+        sweep_chunk_row<double, COH, U>(d, vcur, vnext, n0, cnt, lane, r,
                                                                       s_vs[p & 1][TPN == 3 ? slot : 0], th2, cb);
       else
-        sweep_chunk_node<double, COH, (64 * TPN * NW >= 960 ? 2 : 4)>(d, vcur, vnext, n0, cnt, lane, th2, cb);
+        sweep_chunk_node<double, COH, U>(d, vcur, vnext, n0, cnt, lane, th2, cb);
     }
     th2 = block_sum(th2, s_red);
     double theta;
@@ -660,17 +660,21 @@ struct Variant {
   int nw;     // chunk slots per workgroup
   int grid;   // workgroup cap (0 = one per CU)
   int lds;    // kind 5: LDS levels 0 = when rows average more than 9 blocks, 1 = off, 2 = on
+  int u;      // kind 1 with 8 chunk slots: levels per load group, 1 = two, else four
 };
 
 // Library default (variant 0): the register-resident kernel with the fewest
 // chunk slots per workgroup that still fits one workgroup per CU; the
-// streaming kernel (kind 1) when the problem is larger.
+// streaming kernel (kind 1) when the problem is larger, with eight chunk
+// slots (waves) per workgroup and levels loaded two at a time: the most
+// loads in flight per CU that the registers allow.
 Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu) {
   Variant x;
   x.kind = v & 0xff;
   x.nw = (v >> 8) & 0xff;
   x.grid = (v >> 16) & 0xff;
   x.lds = (v >> 24) & 0x3;
+  x.u = (v >> 26) & 0x3;
   if (x.kind == 0) {
     const int64_t nch = ((int64_t)n_nodes + 63) / 64;
     const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
@@ -684,6 +688,10 @@ Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu) {
         if (x.nw == 0) x.nw = nw;
         break;
       }
+    }
+    if (x.kind == 1 && x.nw == 0 && x.u == 0) {
+      x.nw = 8;
+      x.u = 1;
     }
   }
   if (x.nw == 0) x.nw = (x.kind == 3) ? 16 : (x.kind == 4 ? 5 : (x.kind == 1 ? 2 : (x.kind == 5 ? 2 : 1)));
@@ -711,9 +719,10 @@ hipError_t launch_persistent(void (*kern)(GridArgs), int threads, int nw, const 
   return hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)g), dim3(threads), params, 0, st);
 }
 
-template <int TPN, int NW>
+template <int TPN, int NW, int... U>
 hipError_t launch_grid(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool single, hipStream_t st) {
-  return launch_persistent(k_vfpi_grid<TPN, NW>, 64 * TPN * NW, NW, ga, grid_req, num_cu, n_nodes, single, st);
+  return launch_persistent(k_vfpi_grid<TPN, NW, U...>, 64 * TPN * NW, NW, ga, grid_req, num_cu, n_nodes, single,
+                           st);
 }
 
 template <int NW>
@@ -819,10 +828,14 @@ hipError_t launch_variant(const Variant& vr, const GridArgs& ga, int num_cu, int
     case 1:
       return (vr.nw <= 1)   ? launch_grid<1, 1>(ga, vr.grid, num_cu, N, false, stream)
              : (vr.nw <= 2) ? launch_grid<1, 2>(ga, vr.grid, num_cu, N, false, stream)
-                            : launch_grid<1, 4>(ga, vr.grid, num_cu, N, false, stream);
+             : (vr.nw <= 4) ? launch_grid<1, 4>(ga, vr.grid, num_cu, N, false, stream)
+             : (vr.nw <= 8) ? (vr.u == 1 ? launch_grid<1, 8, 2>(ga, vr.grid, num_cu, N, false, stream)
+                                         : launch_grid<1, 8>(ga, vr.grid, num_cu, N, false, stream))
+                            : launch_grid<1, 16>(ga, vr.grid, num_cu, N, false, stream);
     case 2:
-      return (vr.nw <= 1) ? launch_grid<3, 1>(ga, vr.grid, num_cu, N, false, stream)
-                          : launch_grid<3, 2>(ga, vr.grid, num_cu, N, false, stream);
+      return (vr.nw <= 1)   ? launch_grid<3, 1>(ga, vr.grid, num_cu, N, false, stream)
+             : (vr.nw <= 2) ? launch_grid<3, 2>(ga, vr.grid, num_cu, N, false, stream)
+                            : launch_grid<3, 4>(ga, vr.grid, num_cu, N, false, stream);
     case 3:
       return (vr.nw <= 4) ? launch_grid<1, 4>(ga, 1, num_cu, N, true, stream)
                           : launch_grid<1, 16>(ga, 1, num_cu, N, true, stream);

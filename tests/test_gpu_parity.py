@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-9
 
 # kind | chunk slots << 8 | workgroup cap << 16 | LDS levels (kind 5: 1 off, 2 on) << 24
+# | load group (kind 1, 8 slots: 1 = two levels) << 26
 VARIANTS = {
     "wg1_node16": 3,
     "wg1_node4": 3 | (4 << 8),
@@ -27,6 +28,10 @@ VARIANTS = {
     "grid_row1_cap16": 2 | (16 << 16),
     "grid_row2_cap8": 2 | (2 << 8) | (8 << 16),
     "grid_node2_cap3": 1 | (2 << 8) | (3 << 16),
+    "grid_node8": 1 | (8 << 8),
+    "grid_node8_u2": 1 | (8 << 8) | (1 << 26),
+    "grid_node16": 1 | (16 << 8),
+    "grid_row4": 2 | (4 << 8),
     "regs_node1": 5 | (1 << 8),
     "regs_node2": 5 | (2 << 8),
     "regs_node4": 5 | (4 << 8),
@@ -225,8 +230,24 @@ def test_beyond_register_resident_grid():
     torch.cuda.synchronize()
     # refused before anything was enqueued: v and the stats record untouched
     assert torch.equal(v, v_in) and torch.equal(st, sentinel)
-    for variant in (0, 1 | (4 << 8)):
-        _compare(p, 3, variant)
+    for variant in (0, 1 | (4 << 8), 1 | (8 << 8), 1 | (16 << 8)):
+        _compare(p, 10, variant)
+
+
+@pytest.mark.parametrize("which", ["cloth384", "fem128x64x16"])
+def test_streaming_default_at_scale(which):
+    """Past the register-resident grid (more than 2,048 chunks) the library
+    default is the streaming kernel with eight chunk slots: a 384 x 384 cloth
+    draped over spheres (147,456 nodes) and a 128 x 64 x 16-cell FEM block
+    (142,545 nodes), 10 sweeps, element by element against the oracle."""
+    if which == "cloth384":
+        sc, x, v = scenes.cloth_drape(384, 0)
+    else:
+        sc, x, v = scenes.fem_block((128, 64, 16), 0)
+    p = sc.assemble(x, v)
+    assert (p.n_nodes + 63) // 64 > 2048
+    for variant in (0, 1 | (16 << 8)):
+        _compare(p, 10, variant)
 
 
 def test_reuse_w_matches_oracle_with_previous_row_sums():
