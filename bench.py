@@ -772,8 +772,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sweeps", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--variant", type=int, default=0, help="launch variant of the FEM headline (0: library default)")
-    ap.add_argument("--cloth-variant", type=int, default=0, help="launch variant of the cloth128 leg (0: autotuned)")
+    ap.add_argument("--variant", type=lambda x: int(x, 0), default=0, help="launch variant of the FEM headline (0: library default)")
+    ap.add_argument("--cloth-variant", type=lambda x: int(x, 0), default=0, help="launch variant of the cloth128 leg (0: autotuned)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-cores", type=int, default=0, help="0: every core allotted to the job, at most 16")
     ap.add_argument("--no-cpu", action="store_true")
@@ -785,7 +785,7 @@ def main():
     ap.add_argument("--no-scaling", action="store_true", help="skip the size sweep")
     ap.add_argument("--no-rollout", action="store_true", help="skip the batched rollout divergence")
     ap.add_argument("--scaling-only", action="store_true", help="only the size sweep (for counter runs)")
-    ap.add_argument("--batched-variant", type=int, default=0)
+    ap.add_argument("--batched-variant", type=lambda x: int(x, 0), default=0)
     ap.add_argument("--rollout-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")

@@ -205,8 +205,13 @@ int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, const vfpi_cont
  * FP32 values.  env_order (device [n_env] permutation, or NULL) is the order
  * in which the persistent kernel's work queue hands out envs (largest first is
  * a good choice).  Launch kinds (opts.variant): 1 lane per node, 2 lane per
- * row, 3 lane per node with two workgroups per CU.  per_env_stats: device
- * [n_env].  Every option applies to
+ * row, 3 lane per node with two workgroups per CU, 4 lane per node with the
+ * environment's iterate in LDS: 8 waves per workgroup (the first 512 nodes
+ * keep their first 9 block levels of A in registers for the whole step, the
+ * rest stream A two levels at a time, four with load group 1 << 26) or 16
+ * waves (all of A streamed); environments of up to 3,072 nodes, larger ones
+ * run kind 1's loop in the same launch; 0 = kind 4 with 8 waves.
+ * per_env_stats: device [n_env].  Every option applies to
  * every env; each env stops on its own theta.  W modes: FROBENIUS,
  * USER_SCALAR.  Errors as vfpi_step. */
 int vfpi_step_batched(vfpi_ctx* ctx, int32_t n_env, const int32_t* env_node_off,

@@ -48,7 +48,7 @@ PLAIN_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 2 | (1 << 8), 2 | 
                     1 | (2 << 8) | (128 << 16), 1 | (4 << 8) | (128 << 16), 3 | (16 << 8), 3 | (4 << 8),
                     5 | (1 << 8), 5 | (2 << 8), 5 | (4 << 8), 5 | (5 << 8), 5 | (6 << 8), 5 | (8 << 8)]
 BATCHED_CANDIDATES = [1 | (1 << 8), 1 | (2 << 8), 1 | (4 << 8), 1 | (8 << 8), 2 | (1 << 8), 2 | (2 << 8),
-                      3 | (4 << 8), 3 | (8 << 8)]
+                      3 | (4 << 8), 3 | (8 << 8), 4 | (16 << 8), 4 | (8 << 8), 4 | (8 << 8) | (1 << 26)]
 
 
 def _load():

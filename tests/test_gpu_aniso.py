@@ -54,13 +54,14 @@ def test_aniso_with_omega_chebyshev_bb():
         say(f"  random700 aniso {opts}: rel_v={ev:.2e} rel_lam={el:.2e} ties={ties}")
 
 
-def test_batched_aniso():
+@pytest.mark.parametrize("variant", [0, 4 | (16 << 8)])
+def test_batched_aniso(variant):
     envs = [_aniso(scenes.random_problem(n, nc, s, degree=4.0, phi_scale=0.5, n_d_contacts=nd), s)
             for s, (n, nc, nd) in enumerate([(90, 40, 10), (300, 100, 0), (500, 200, 30)])]
     envs.append(scenes.random_problem(200, 80, 9, degree=4.0, phi_scale=0.5))  # isotropic env in the batch
     batch = scenes.concat_problems(envs)
     L = 30
-    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True)
+    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True, variant=variant)
     worst = 0.0
     for e, pe in enumerate(envs):
         ref = oracle.vfpi(pe, max_iters=L, fixed_iters=True)

@@ -16,7 +16,9 @@ TOL = 1e-4
 
 VARIANTS = {"node1": 1 | (1 << 8), "node2": 1 | (2 << 8), "node4": 1 | (4 << 8), "node8": 1 | (8 << 8),
             "row1": 2 | (1 << 8), "row2": 2 | (2 << 8), "node4_3wg": 1 | (4 << 8) | (3 << 16),
-            "node4_occ4": 3 | (4 << 8), "node8_occ4": 3 | (8 << 8)}
+            "node4_occ4": 3 | (4 << 8), "node8_occ4": 3 | (8 << 8),
+            "lds16": 4 | (16 << 8), "lds8_regs": 4 | (8 << 8), "lds8_regs_u4": 4 | (8 << 8) | (1 << 26)}
+LDS_VARIANTS = [4 | (16 << 8), 4 | (8 << 8)]
 
 
 def _envs_small():
@@ -112,7 +114,7 @@ def test_batched_bad_env_isolated():
     _check_envs(batch, v, lam, st, 10, envs_idx=good)
 
 
-@pytest.mark.parametrize("variant", [0, 3 | (8 << 8)])
+@pytest.mark.parametrize("variant", [0, 3 | (8 << 8), 4 | (16 << 8)])
 def test_full_batch_sampled(variant):
     envs = [sc.assemble(x, v) for sc, x, v in scenes.cloth_cfg4_envs(0)]
     batch = scenes.concat_problems(envs)
@@ -125,7 +127,33 @@ def test_full_batch_sampled(variant):
         f"worst rel {worst:.2e}")
 
 
-def test_graph_capture_replays_match_eager():
+@pytest.mark.parametrize("variant", LDS_VARIANTS)
+def test_lds_kernel_environment_beyond_lds(variant):
+    """The LDS-resident kernel holds environments of up to 3,072 nodes; a
+    60 x 60 cloth (3,600 nodes) in the same batch runs the global-memory loop
+    of the same launch.  Both against the oracle, with and without
+    convergence by tolerance."""
+    envs = [sc.assemble(x, v) for sc, x, v in scenes.cloth_cfg4_envs(3, n_env=6, smin=20, smax=48)]
+    sc, x, v = scenes.cloth_cfg4_envs(4, n_env=1, smin=60, smax=60)[0]
+    envs.insert(2, sc.assemble(x, v))
+    assert max(e.n_nodes for e in envs) > 3072
+    batch = scenes.concat_problems(envs)
+    L = 40
+    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True, variant=variant)
+    worst = _check_envs(batch, v, lam, st, L)
+    for e, pe in enumerate(envs):  # every contact counted once, in one branch
+        assert st[e]["n_open"] + st[e]["n_stick"] + st[e]["n_slip"] == pe.n_contacts, (e, st[e])
+    v2, lam2, st2 = run_batched(batch, max_iters=5000, tol=3e-5, variant=variant)
+    for e, pe in enumerate(envs):
+        ref = oracle.vfpi(pe, max_iters=5000, tol=3e-5)
+        assert st2[e]["status"] == _abi.VFPI_S_CONVERGED, (e, st2[e])
+        n0, n1 = batch.env_node_off[e], batch.env_node_off[e + 1]
+        gate(v2[3 * n0:3 * n1], ref["v"], 1e-3, f"env {e} converged v")
+    say(f"  lds kernel {variant:#x}: sizes {[e.n_nodes for e in envs]}, worst rel {worst:.2e}")
+
+
+@pytest.mark.parametrize("variant", [0] + LDS_VARIANTS)
+def test_graph_capture_replays_match_eager(variant):
     """The batched step captured in a HIP graph (torch.cuda.CUDAGraph) gives
     the eager result on every replay, with eager work and syncs in between."""
     envs = _envs_small()
@@ -137,7 +165,7 @@ def test_graph_capture_replays_match_eager():
     v0 = v.clone()
     lam = torch.empty(3 * p.n_contacts, dtype=torch.float32, device=dev)
     st = vf.new_stats(batch.n_env, dev)
-    opt = dict(max_iters=15, fixed_iters=True)
+    opt = dict(max_iters=15, fixed_iters=True, variant=variant)
     s.step_batched(batch.n_env, no, co, A, b, Jc, v, lam, stats=st, **opt)
     torch.cuda.synchronize()
     ref_v, ref_l = v.clone(), lam.clone()

@@ -48,12 +48,13 @@ def test_chebyshev_converged_fewer_sweeps():
     assert st["iters"] < plain["iters"]
 
 
-def test_batched_chebyshev_parity():
+@pytest.mark.parametrize("variant", [0, 4 | (16 << 8)])
+def test_batched_chebyshev_parity(variant):
     from tests.test_gpu_batched import _envs_small
     envs = _envs_small()
     batch = scenes.concat_problems(envs)
     L = 30
-    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True, cheby_ls=4, cheby_u=0.9)
+    v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True, cheby_ls=4, cheby_u=0.9, variant=variant)
     for e, pe in enumerate(envs):
         ref = vfpi_chebyshev(pe, max_iters=L, fixed_iters=True, l_s=4, u=0.9)
         n0, n1 = batch.env_node_off[e], batch.env_node_off[e + 1]

@@ -103,7 +103,7 @@ def test_batched_d_contacts():
     envs.append(scenes.cloth_pair_collision(2, side=16))
     batch = scenes.concat_problems(envs)
     L = 30
-    for var in (1 | (2 << 8), 1 | (8 << 8), 2 | (1 << 8)):
+    for var in (1 | (2 << 8), 1 | (8 << 8), 2 | (1 << 8), 4 | (16 << 8), 4 | (8 << 8)):
         v, lam, st = run_batched(batch, max_iters=L, fixed_iters=True, variant=var)
         worst = 0.0
         for e, pe in enumerate(envs):
