@@ -431,12 +431,19 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
 // most NW chunks).  A lane keeps its node's first KC block levels of A and
 // its own g~, t and u in registers for the whole solve; only s = W t goes
 // through memory, written as whole lines through LDS and gathered coherently
-// by the neighbours' products.  Same sweeps and arithmetic order as k_adjoint.
+// by the neighbours' products.  The contact term of G^T is formed once, before
+// the iteration: a contact node's 3x3 matrix M = (w_i / gamma) R^T D_P^T R
+// (D_P of the taped branch, for the elliptic cone with its closest-point
+// multiplier solved once), kept in LDS, so a sweep applies t = u - M u with no
+// further reads of the contact record or the tape.  Same sweeps as k_adjoint
+// (the contact term in another rounding order).
 template <int NW, int KC>
 __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   __shared__ double s_red[NW];
   __shared__ double s_poll[3 * NW];  // see grid_sum
   __shared__ double s_out[NW][192];
+  __shared__ double s_M[NW][9][64];
+  __shared__ double s_gw[NW][6][64];  // g~ (3) and W (3) of the lane's node
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
   const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -491,9 +498,44 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   }
   const int64_t off_tail = off;
   const int m = act ? a.cmap[i] : -1;
-  double w3[3] = {0.0, 0.0, 0.0};
-  if (act)
-    for (int r = 0; r < 3; ++r) w3[r] = a.w[3 * i + r];
+  {
+    double w3[3] = {0.0, 0.0, 0.0};
+    if (act)
+      for (int r = 0; r < 3; ++r) w3[r] = a.w[3 * i + r];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) s_gw[slot][3 + r][lane] = w3[r];
+    // M = f R^T D_P^T R, f = w_i / gamma (zero off contacts: t = u exactly)
+    double M[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (m >= 0) {
+      const double* R = a.cpack + kPack * (int64_t)m;
+      const double f = w3[0] / R[11];
+      double Dt[3][3];  // Dt[.][k] = D_P^T e_k
+      for (int k = 0; k < 3; ++k) {
+        double x[3] = {0.0, 0.0, 0.0}, y[3], dmu, dmu2;
+        x[k] = 1.0;
+        dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, x, y, &dmu, &dmu2);
+        for (int r = 0; r < 3; ++r) Dt[r][k] = y[r];
+      }
+      for (int r = 0; r < 3; ++r)
+        for (int c2 = 0; c2 < 3; ++c2) {
+          double acc = 0.0;
+          for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) acc += R[3 * p + r] * Dt[p][q] * R[3 * q + c2];
+          M[3 * r + c2] = f * acc;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) s_M[slot][e][lane] = M[e];
+  }
+  auto W = [&](int r) { return s_gw[slot][3 + r][lane]; };
+  // t = G^T u for this lane's node: u - M u
+  auto gtm = [&](const double u[3], double out[3]) {
+    double Mr[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Mr[e] = s_M[slot][e][lane];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) out[r] = u[r] - (Mr[3 * r] * u[0] + Mr[3 * r + 1] * u[1] + Mr[3 * r + 2] * u[2]);
+  };
   // y = A x for this lane's row (every thread calls)
   auto spmv = [&](const double* x, double out[3]) {
     double xs[KC][3];
@@ -535,21 +577,24 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       const double gi = 1.0 / R[11];
       for (int r = 0; r < 3; ++r) e3[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
     }
-    const double p3[3] = {w3[0] * e3[0], w3[1] * e3[1], w3[2] * e3[2]};
+    const double p3[3] = {W(0) * e3[0], W(1) * e3[1], W(2) * e3[2]};
     publish(a.S[1], p3);
     grid_barrier(a.slots, G, lb, ++seq, s_poll);
   }
   // phase B: g~ = g_v - e + A p; u0 = g~, t0 = G^T u0, s0 = W t0
-  double gt[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0}, tt[3] = {0.0, 0.0, 0.0};
+  double uu[3] = {0.0, 0.0, 0.0}, tt[3] = {0.0, 0.0, 0.0};
   {
     double Ap[3] = {0.0, 0.0, 0.0};
     if (a.gl) spmv(a.S[1], Ap);
+    double gt[3] = {0.0, 0.0, 0.0};
     if (act) {
       for (int r = 0; r < 3; ++r) gt[r] = a.gl ? a.gv[3 * i + r] - e3[r] + Ap[r] : a.gv[3 * i + r];
-      gt_node(a, i, m, gt, tt);
+      gtm(gt, tt);
       for (int r = 0; r < 3; ++r) uu[r] = gt[r];
     }
-    const double s3[3] = {w3[0] * tt[0], w3[1] * tt[1], w3[2] * tt[2]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) s_gw[slot][r][lane] = gt[r];
+    const double s3[3] = {W(0) * tt[0], W(1) * tt[1], W(2) * tt[2]};
     publish(a.S[0], s3);
     grid_barrier(a.slots, G, lb, ++seq, s_poll);
   }
@@ -562,8 +607,8 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       double th2 = 0.0;
       if (act) {
         double un[3], tn[3];
-        for (int r = 0; r < 3; ++r) un[r] = gt[r] + tt[r] - As[r];
-        gt_node(a, i, m, un, tn);
+        for (int r = 0; r < 3; ++r) un[r] = s_gw[slot][r][lane] + tt[r] - As[r];
+        gtm(un, tn);
         for (int r = 0; r < 3; ++r) {
           const double d = un[r] - uu[r];
           th2 += d * d;
@@ -571,7 +616,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
           tt[r] = tn[r];
         }
       }
-      const double s3[3] = {w3[0] * tt[0], w3[1] * tt[1], w3[2] * tt[2]};
+      const double s3[3] = {W(0) * tt[0], W(1) * tt[1], W(2) * tt[2]};
       publish(a.S[nxt], s3);
       th2 = block_sum(th2, s_red);
       const bool stop = grid_residual_step(a.slots, G, lb, ++seq, th2, l, a.max_iters, a.fixed, a.tol, a.stats, s_poll);
@@ -589,7 +634,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   double q[3] = {uu[0], uu[1], uu[2]};
   if (m >= 0) {
     const double* R = a.cpack + kPack * (int64_t)m;
-    const double wb = w3[0];
+    const double wb = W(0);
     double rr[3], y[3], dmu, dmu2;
     for (int k = 0; k < 3; ++k) {
       rr[k] = R[3 * k] * (wb * uu[0]) + R[3 * k + 1] * (wb * uu[1]) + R[3 * k + 2] * (wb * uu[2]);
@@ -604,7 +649,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   }
   double bb[3];
   for (int r = 0; r < 3; ++r) {
-    bb[r] = w3[r] * q[r];
+    bb[r] = W(r) * q[r];
     a.grad_b[3 * i + r] = bb[r];
   }
   if (a.grad_A) {
