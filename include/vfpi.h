@@ -65,6 +65,10 @@ extern "C" {
 #define VFPI_S_BAD_PATTERN      0x200  /* column index out of range / out of env */
 #define VFPI_S_BAD_W            0x400  /* user W not positive, or unequal on a contact node */
 #define VFPI_S_BAD_MU           0x800  /* mu < 0                               */
+#define VFPI_S_SYNC_TIMEOUT    0x1000  /* a workgroup of the persistent kernel waited
+                                          for another for seconds and gave up; the
+                                          results are not valid (not expected to
+                                          happen: a guard against a hang) */
 
 /* ---- step-size matrix W (Sec. IV-C) ------------------------------------ */
 #define VFPI_W_FROBENIUS    0  /* w_d = a_dd/||A_d*||^2, shared on contact nodes (Sec. IV-C.1) */
@@ -132,13 +136,18 @@ typedef struct {
   int32_t reuse_w;       /* 1: keep the row sums a_dd, ||A_d*||^2 of the previous
                             call on this context (W reuse across steps, Sec. IV-C) */
   int32_t variant;       /* launch variant: kind | chunk slots << 8 | workgroup cap << 16
-                            | LDS levels << 24 | load group << 26.
+                            | LDS levels << 24 | load group << 26 | sync << 28.
                             vfpi_step kinds: 1 grid, lane per node; 2 grid, lane per row;
                             3, 4 the same in one workgroup; 5 grid, the node's first
                             block levels of A in registers and the next ones in LDS
                             (LDS levels: 0 when rows average more than 9 blocks, 1 off,
                             2 on; refused with VFPI_E_OPTS when the grid needs more
-                            than one workgroup per CU).  Load group (kind 1 with 8
+                            than one workgroup per CU; without Chebyshev, BB step sizes
+                            and D-contacts it takes the stop test of sweep l after
+                            sweep l + 1 and synchronizes a workgroup only with the
+                            workgroups owning its rows' columns, unless sync = 1, which
+                            keeps a full grid reduction after every sweep; the results
+                            are the same).  Load group (kind 1 with 8
                             chunk slots): levels of A loaded together, 1 two, else
                             four.  0 = library
                             default: kind 5 with the fewest chunk slots (2, 4, 5, 6, 8)

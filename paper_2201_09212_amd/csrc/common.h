@@ -26,13 +26,15 @@ enum { BR_OPEN = 0, BR_STICK = 1, BR_SLIP = 2 };
 constexpr int kWave = 64;
 constexpr int kPack = 13;  // per-contact record: R (9), phi, mu, gamma, mu2
 constexpr int kMaxGridSlots = 1024;  // workgroups of a persistent launch (slots per parity)
-// Slot memory of the grid reductions: region 0 = [2][kMaxGridSlots] slots for
-// the residual / barrier, each slot alone in kSlotPad words (256 bytes) so
-// that the workgroups polling one slot do not contend with those polling its
+// Slot memory of the grid reductions: region 0 = [4][kMaxGridSlots] slots for
+// the residual / barrier (rings 0-1 for the synchronous reduction, 0-3 for the
+// lagged one), each slot alone in kSlotPad words (256 bytes) so that the
+// workgroups polling one slot do not contend with those polling its
 // neighbours; region 1 = [2][3][kMaxGridSlots] for the three dot products of
 // the Barzilai-Borwein step size.
 constexpr int kSlotPad = 32;
-constexpr int kBBSlotOffset = 2 * kMaxGridSlots * kSlotPad;
+constexpr int kSlotRings = 4;
+constexpr int kBBSlotOffset = kSlotRings * kMaxGridSlots * kSlotPad;
 constexpr int kSlotWords = kBBSlotOffset + 6 * kMaxGridSlots;
 
 VFPI_DEV uint64_t ballot(bool p) { return __ballot(p); }

@@ -18,7 +18,7 @@ __global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t*
   const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i < n_nodes; i += stride) cmap[i] = -1;
-  for (int64_t i = i0; i < 2 * kMaxGridSlots; i += stride) slots[i * kSlotPad] = 0ull;  // region 0 slots
+  for (int64_t i = i0; i < kSlotRings * kMaxGridSlots; i += stride) slots[i * kSlotPad] = 0ull;  // region 0
   for (int64_t i = i0; i < 6 * kMaxGridSlots; i += stride) slots[kBBSlotOffset + i] = 0ull;
   if (i0 == 0) {
     flags[0] = 0;
@@ -87,6 +87,9 @@ struct GridArgs {
   double* avbuf;                      // [n] A v^l of the previous sweep (own DOFs)
   const unsigned long long* amax;     // max_d sum_j |a_dj| from the setup
   double* tape_w;                     // nullable: receives the final alpha
+  // lagged residual (k_vfpi_regs with LAG): contact results of the last two
+  // sweeps, [2][n_contacts][8] (lambda, lambda*, branch)
+  double* lring;
 };
 
 // Persistent V-FPI kernel: the whole sweep loop of one step.  TPN = threads
@@ -346,7 +349,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
 // Barzilai-Borwein step sizes (W = alpha^l I, see k_vfpi_bb), with the node's
 // own v^{l-1} and A v^{l-1} kept in registers and one more grid reduction
 // (the three dot products) per sweep.
-template <int NW, int KC, int KL, int U, bool COH, bool CH, bool BB = false>
+template <int NW, int KC, int KL, int U, bool COH, bool CH, bool BB = false, bool LAG = false>
 __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   // Registers hold what every sweep streams through the FMA chains: A's first
   // KC levels, the gathered neighbour values and the node's own iterate.  The
@@ -363,6 +366,11 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   __shared__ double s_lam[NW][6][64];     // lambda, lambda* of the last sweep
   __shared__ double s_al[KL > 0 ? NW : 1][KL > 0 ? KL : 1][9][64];  // levels KC..KC+KL-1
   __shared__ int s_cl[KL > 0 ? NW : 1][KL > 0 ? KL : 1][64];
+  // LAG (S-contacts, no Chebyshev, no BB, more than one workgroup): the stop
+  // test of sweep l is taken after sweep l + 1, and between sweeps a
+  // workgroup waits only for its neighbours (lag_sync in gridsync.h)
+  __shared__ uint32_t s_nbm[LAG ? kMaxGridSlots / 32 : 1];
+  __shared__ int s_lflag;
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
   const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -459,6 +467,22 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   // BB: alpha^1 from the Gershgorin bound; v^{l-1} and A v^{l-1} of the own node
   double alpha = BB ? 1.0 / __builtin_bit_cast(double, (uint64_t)*a.amax) : 0.0;
   double vq[3] = {0.0, 0.0, 0.0}, aq[3] = {0.0, 0.0, 0.0};
+  if constexpr (LAG) {
+    // neighbour workgroups: the owners of the columns of this workgroup's
+    // rows (chunk q belongs to the workgroup lg with lg nch / G <= q, i.e.
+    // lg = ((q + 1) G - 1) / nch)
+    for (int k = threadIdx.x; k < kMaxGridSlots / 32; k += blockDim.x) s_nbm[k] = 0u;
+    __syncthreads();
+    if (act) {
+      const int64_t r1 = d.row_ptr[i + 1];
+      for (int64_t k = d.row_ptr[i]; k < r1; ++k) {
+        const int64_t q = (int64_t)d.col_idx[k] / 64;
+        const int lg = (int)(((q + 1) * G - 1) / nch);
+        if (lg != lb) atomicOr(&s_nbm[lg >> 5], 1u << (lg & 31));
+      }
+    }
+    __syncthreads();
+  }
   for (int l = 1;; ++l) {
     const double nu = CH ? ch.next_nu(l) : 1.0;
     double xs[KC][3];
@@ -540,7 +564,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         vn[r] = vs[r];
       }
     }
-    if (has_d) {
+    if (!LAG && has_d) {
       // node-node contacts in two phases: the nodes of D pairs publish v*,
       // and after a grid barrier both nodes of a pair read the same two
       // values, so they form the same lambda
@@ -582,13 +606,20 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         cr.mu2 = s_cr[slot][12][lane];
         double lam[3], ls[3];
         br = contact_solve<double>(cr, vs[0], vs[1], vs[2], d.proj, lam, ls);
+        double* rg = LAG ? a.lring + ((int64_t)(l & 1) * a.n_contacts + m) * 8 : nullptr;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
           vn[r] = vs[r] + (BB ? alpha : s_bw[slot][3 + r][lane]) * F;
-          s_lam[slot][r][lane] = lam[r];
-          s_lam[slot][3 + r][lane] = ls[r];
+          if (LAG) {
+            rg[r] = lam[r];
+            rg[3 + r] = ls[r];
+          } else {
+            s_lam[slot][r][lane] = lam[r];
+            s_lam[slot][3 + r][lane] = ls[r];
+          }
         }
+        if (LAG) rg[6] = (double)br;
       }
       if (CH && ch.ls) {
 #pragma unroll
@@ -615,14 +646,60 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) vo[r] = vn[r];
     th2 = block_sum(th2, s_red);
-    double theta;
-    const bool stop = grid_residual_step(a.slots, G, lb, has_d ? 2 * l : l, th2, l, a.max_iters, a.fixed, a.tol,
-                                         a.stats, s_poll, &theta);
-    double* t = vcur;
-    vcur = vnext;
-    vnext = t;
-    if (stop) break;
-    if (CH) ch.observe(theta);
+    if constexpr (LAG) {
+      const LagResult lr = lag_sync(a.slots, G, lb, l, th2, a.max_iters, a.fixed, a.tol, s_nbm, s_poll, &s_lflag);
+      if (lr.stop == 0) {
+        double* t = vcur;
+        vcur = vnext;
+        vnext = t;
+        continue;
+      }
+      // Alg. 1 stopped at sweep s = l (results of this sweep) or l - 1 (v^l
+      // is in vcur, the contact results in the ring's other half)
+      const int s = lr.stop;
+      if (lr.status == VFPI_S_SYNC_TIMEOUT) {
+        if (threadIdx.x == 0) atomicOr(&a.stats->status, VFPI_S_SYNC_TIMEOUT);
+      } else if (lb == 0 && threadIdx.x == 0) {
+        a.stats->iters = s;
+        a.stats->status = lr.status;
+        a.stats->theta = lr.theta;
+      }
+      int cb[3] = {0, 0, 0};
+      if (act) {
+        if (s != l) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) vo[r] = ldv<COH>(vcur + 3 * i + r);
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          a.v_user[3 * i + r] = vo[r];
+          if (a.tape_v) a.tape_v[3 * i + r] = vo[r];
+        }
+        if (m >= 0) {
+          const double* rg = a.lring + ((int64_t)(s & 1) * a.n_contacts + m) * 8;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            d.lambda[3 * (int64_t)m + r] = rg[r];
+            if (d.tape_lamstar) d.tape_lamstar[3 * (int64_t)m + r] = rg[3 + r];
+          }
+          const int bs = (int)rg[6];
+          if (d.tape_branch) d.tape_branch[m] = bs;
+          cb[bs] = 1;
+        }
+      }
+      block_sum4_int(cb[0], cb[1], cb[2], s_ired);
+      add_counts(a.stats, cb[0], cb[1], cb[2]);
+      return;
+    } else {
+      double theta;
+      const bool stop = grid_residual_step(a.slots, G, lb, has_d ? 2 * l : l, th2, l, a.max_iters, a.fixed,
+                                           a.tol, a.stats, s_poll, &theta);
+      double* t = vcur;
+      vcur = vnext;
+      vnext = t;
+      if (stop) break;
+      if (CH) ch.observe(theta);
+    }
   }
   int cb[3] = {0, 0, 0};
   if (act && m >= 0 && owner) {
@@ -661,6 +738,7 @@ struct Variant {
   int grid;   // workgroup cap (0 = one per CU)
   int lds;    // kind 5: LDS levels 0 = when rows average more than 9 blocks, 1 = off, 2 = on
   int u;      // kind 1 with 8 chunk slots: levels per load group, 1 = two, else four
+  int sync;   // kind 5: 1 = the residual reduction and barrier of every sweep (no lag)
 };
 
 // Library default (variant 0): the register-resident kernel with the fewest
@@ -675,6 +753,7 @@ Variant decode_variant(int32_t v, int32_t n_nodes, int num_cu) {
   x.grid = (v >> 16) & 0xff;
   x.lds = (v >> 24) & 0x3;
   x.u = (v >> 26) & 0x3;
+  x.sync = (v >> 28) & 0x1;
   if (x.kind == 0) {
     const int64_t nch = ((int64_t)n_nodes + 63) / 64;
     const int64_t cap = num_cu < kMaxGridSlots ? num_cu : kMaxGridSlots;
@@ -750,7 +829,7 @@ int64_t regs_grid(int NW, int grid_req, int num_cu, int n_nodes) {
 // fit).  KC register levels and KL LDS levels per lane; the rest streamed in
 // groups of U levels.
 template <int NW, int KC, int KL, int U, bool BB>
-hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, hipStream_t st) {
+hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool sync, hipStream_t st) {
   const int64_t g = regs_grid(NW, grid_req, num_cu, n_nodes);
   if (g < 0) return hipErrorInvalidValue;
   GridArgs arg = ga;
@@ -771,8 +850,12 @@ hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
         hipLaunchKernelGGL((k_vfpi_regs<NW, KC, KL, U, false, false>), dim3(1), dim3(64 * NW), 0, st, ga);
       return hipGetLastError();
     }
-    kern = ch ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
-              : (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>;
+    // the lagged residual needs no Chebyshev (nu of sweep l + 1 depends on
+    // theta_l) and S-contacts only (D pairs meet in a grid barrier)
+    const bool lag = !ch && !sync && ga.d.cpair == nullptr;
+    kern = ch    ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
+           : lag ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, false, false, true>
+                 : (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>;
   }
   return hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * NW), params, 0, st);
 }
@@ -786,18 +869,18 @@ hipError_t launch_kind5(const Variant& vr, const GridArgs& ga, int num_cu, int N
                         hipStream_t stream) {
   const bool kl = vr.lds == 2 || (vr.lds == 0 && long_rows);
   if (kl)
-    return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, stream)
-           : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, stream)
-           : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1, BB>(ga, vr.grid, num_cu, N, stream)
-           : (vr.nw <= 5) ? launch_regs<5, 6, 3, 2, BB>(ga, vr.grid, num_cu, N, stream)
-           : (vr.nw <= 6) ? launch_regs<6, 4, 2, 2, BB>(ga, vr.grid, num_cu, N, stream)
-                          : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream);
-  return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, stream)
-         : (vr.nw <= 2) ? launch_regs<2, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, stream)
-         : (vr.nw <= 4) ? launch_regs<4, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, stream)
-         : (vr.nw <= 5) ? launch_regs<5, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream)
-         : (vr.nw <= 6) ? launch_regs<6, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream)
-                        : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, stream);
+    return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 5) ? launch_regs<5, 6, 3, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 6) ? launch_regs<6, 4, 2, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+                          : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
+  return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+         : (vr.nw <= 2) ? launch_regs<2, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+         : (vr.nw <= 4) ? launch_regs<4, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+         : (vr.nw <= 5) ? launch_regs<5, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+         : (vr.nw <= 6) ? launch_regs<6, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+                        : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
 }
 
 // Barzilai-Borwein step sizes: the register-resident kernel (kind 5) or the
@@ -942,6 +1025,7 @@ extern "C" int vfpi_step(vfpi_ctx* ctx, const vfpi_bsr* A, const double* b, cons
   ga.avbuf = ctx->adj;
   ga.amax = reinterpret_cast<const unsigned long long*>(ctx->sync + SY_AMAX);
   ga.tape_w = tv.w;
+  ga.lring = ctx->adj;
 
   vfpi_mark(ctx, 1, stream);
   const bool long_rows = A->nnzb > 9 * (int64_t)N;

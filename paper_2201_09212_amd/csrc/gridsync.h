@@ -147,6 +147,97 @@ VFPI_DEV bool grid_residual_step(uint64_t* slots, int G, int lb, int seq, double
   return stop;
 }
 
+// ---- lagged residual and neighbour barrier --------------------------------
+// Without Chebyshev acceleration the stop test of sweep l can wait: after
+// publishing sweep l's partial, a workgroup waits only for the workgroups
+// that own columns of its rows (its neighbours, a symmetric relation since A
+// is symmetric) to have published sweep l, which is all that sweep l + 1's
+// gathers need, and for every workgroup's partial of sweep l - 1, which is
+// the stop test of sweep l - 1, taken one sweep late.  When it stops, sweep
+// l - 1's results are still at hand: v^l is the buffer sweep l read, the
+// contact results are double-buffered by sweep parity.  Sweep l + 1 of
+// workgroup X overwrites v^l only after X's neighbours, the only readers of
+// X's nodes, have published sweep l.  Slots form a ring of four: a
+// workgroup publishes sweep l + 4 only after every workgroup has published
+// l + 2, which each does only after it has read all partials of sweep l (with
+// three, a workgroup that is not X's neighbour could overwrite the slot of
+// sweep l while X still reads it).  Every wait is bounded (kSpinLimit polls);
+// a workgroup that gives up sets VFPI_S_SYNC_TIMEOUT and leaves the loop, so
+// the kernel ends even if the protocol were broken.
+constexpr int kSpinLimit = 1 << 21;
+
+VFPI_DEV uint64_t* ring_slot(uint64_t* slots, int l, int k) {
+  return slots + ((int64_t)(l & (kSlotRings - 1)) * kMaxGridSlots + k) * kSlotPad;
+}
+
+// Poll one slot until it carries `tag`; false on timeout.
+VFPI_DEV bool spin_tag(const uint64_t* p, unsigned tag, uint64_t& b) {
+  for (int n = 0; n < kSpinLimit; ++n) {
+    b = ld_relaxed(p);
+    if ((b & 0xffull) == tag) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
+
+struct LagResult {
+  int stop;      // sweep at which Alg. 1 stops (0: go on)
+  int status;    // VFPI_S_CONVERGED / VFPI_S_MAXITER (/ VFPI_S_SYNC_TIMEOUT)
+  double theta;  // residual of the stopping sweep
+};
+
+// End of sweep l (every thread calls; th2 = this workgroup's partial, valid
+// in every thread).  nbm: bitmap of the neighbour workgroups (LDS).  s_poll:
+// 3 doubles per wave, s_flag: one int (LDS).
+VFPI_DEV LagResult lag_sync(uint64_t* slots, int G, int lb, int l, double th2, int max_iters, int fixed, double tol,
+                            const uint32_t* nbm, double* s_poll, int* s_flag) {
+  const unsigned tag_l = sync_tag(l), tag_p = sync_tag(l - 1);
+  // the flag's readers of the previous call have all passed the sweep's
+  // barriers since, and its writers below come after the next one
+  if (threadIdx.x == 0) *s_flag = 0;
+  drain();
+  __syncthreads();
+  if (threadIdx.x == 0) st_relaxed(ring_slot(slots, l, lb), tagged(th2, tag_l));
+  const bool last = l >= max_iters;
+  const bool prev = !fixed && l >= 2;
+  double acc_p = 0.0, acc_l = 0.0;
+  bool ok = true;
+  for (int k = threadIdx.x; k < G && ok; k += blockDim.x) {
+    uint64_t b = 0;
+    if (prev) {
+      ok = spin_tag(ring_slot(slots, l - 1, k), tag_p, b);
+      acc_p += untag(b);
+    }
+    if (ok && last) {
+      ok = spin_tag(ring_slot(slots, l, k), tag_l, b);
+      acc_l += untag(b);
+    } else if (ok && ((nbm[k >> 5] >> (k & 31)) & 1u)) {
+      ok = spin_tag(ring_slot(slots, l, k), tag_l, b);
+    }
+  }
+  if (!ok) atomicOr(s_flag, 1);  // read after poll_sum's barrier
+  acc_p = prev ? poll_sum(acc_p, s_poll) : 0.0;
+  __syncthreads();
+  acc_l = last ? poll_sum(acc_l, s_poll) : 0.0;
+  LagResult r = {0, VFPI_S_MAXITER, 0.0};
+  if (*s_flag) {
+    r.stop = l;
+    r.status = VFPI_S_SYNC_TIMEOUT;
+    r.theta = INFINITY;
+    return r;
+  }
+  if (prev && sqrt(acc_p) < tol) {
+    r.stop = l - 1;
+    r.status = VFPI_S_CONVERGED;
+    r.theta = sqrt(acc_p);
+  } else if (last) {
+    r.stop = l;
+    r.theta = sqrt(acc_l);
+    r.status = (!fixed && r.theta < tol) ? VFPI_S_CONVERGED : VFPI_S_MAXITER;
+  }
+  return r;
+}
+
 // Plain grid barrier: every write before it is visible to every workgroup
 // after it (through coherent loads).
 VFPI_DEV void grid_barrier(uint64_t* slots, int G, int lb, int seq, double* s_poll) {

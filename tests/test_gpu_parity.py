@@ -9,7 +9,7 @@ import oracle
 import paper_2201_09212_amd as vf
 import scenes
 from paper_2201_09212_amd import _abi
-from tests.gpu_util import fixed_parity, gate, gpu_step, say, solver_for, upload
+from tests.gpu_util import fixed_parity, gate, gpu_step, say, solver_for, tape_parts, upload
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-9
@@ -262,3 +262,49 @@ def test_reuse_w_matches_oracle_with_previous_row_sums():
     ref = oracle.vfpi(p2, max_iters=40, fixed_iters=True, stats=stats1)
     gate(v2, ref["v"], TOL, "reuse_w v")
     gate(lam2, ref["lam"], TOL, "reuse_w lambda")
+
+
+def _step_all(p, **opt):
+    v, lam, st, tp = gpu_step(p, tape=True, **opt)
+    t = tape_parts(tp, p.n_nodes, p.n_contacts) if p.n_contacts else None
+    return v, lam, st, t
+
+
+@pytest.mark.parametrize("which", ["cloth128", "fem16x16x4", "random700_regs1"])
+def test_lagged_residual_matches_synchronous(which):
+    """The register-resident kernel takes the stop test of sweep l after
+    sweep l + 1 and synchronizes each workgroup with its neighbours only; with
+    the sync bit it reduces over the whole grid after every sweep.  Both must
+    stop on the same sweep with the same results, bit for bit: converged at
+    several tolerances, stopped by max_iters (also at 1 and 2 sweeps), and at
+    a fixed sweep count; the converged runs also against the oracle."""
+    variant = 0
+    if which == "cloth128":
+        sc, x, v = scenes.cloth_cfg2(0)
+        p = sc.assemble(x, v)
+    elif which == "fem16x16x4":
+        sc, x, v = scenes.fem_ctx(0)
+        p = sc.assemble(x, v)
+    else:
+        p = scenes.random_problem(700, 300, 71, degree=5.0, phi_scale=0.5)
+        variant = 5 | (1 << 8)
+    sync = variant | (1 << 28)
+    cases = [dict(max_iters=5000, tol=t) for t in (1e-3, 1e-5, 1e-8)]
+    cases += [dict(max_iters=37, tol=1e-30), dict(max_iters=1, tol=1e-3), dict(max_iters=2, tol=1e-30),
+              dict(max_iters=2, tol=1e30), dict(max_iters=25, fixed_iters=True)]
+    for opt in cases:
+        a = _step_all(p, variant=variant, **opt)
+        b = _step_all(p, variant=sync, **opt)
+        assert a[2] == b[2], (which, opt, a[2], b[2])
+        assert np.array_equal(a[0].view(np.int64), b[0].view(np.int64)), (which, opt)
+        assert np.array_equal(a[1].view(np.int64), b[1].view(np.int64)), (which, opt)
+        if p.n_contacts:
+            for k in ("w", "v", "lam_star", "branch"):
+                assert np.array_equal(np.asarray(a[3][k]).view(np.uint8), np.asarray(b[3][k]).view(np.uint8)), k
+        say(f"  {which} {opt}: iters={a[2]['iters']} status={a[2]['status']} theta={a[2]['theta']:.3e} "
+            f"lagged == synchronous")
+        if not opt.get("fixed_iters") and opt["max_iters"] == 5000:
+            ref = oracle.vfpi(p, max_iters=opt["max_iters"], tol=opt["tol"])
+            assert a[2]["status"] == _abi.VFPI_S_CONVERGED and abs(a[2]["iters"] - ref["iters"]) <= 1
+            if a[2]["iters"] == ref["iters"]:
+                gate(a[0], ref["v"], TOL, f"{which} tol={opt['tol']} v")
