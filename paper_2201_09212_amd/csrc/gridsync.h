@@ -203,17 +203,17 @@ VFPI_DEV LagResult lag_sync(uint64_t* slots, int G, int lb, int l, double th2, i
   double acc_p = 0.0, acc_l = 0.0;
   bool ok = true;
   for (int k = threadIdx.x; k < G && ok; k += blockDim.x) {
-    uint64_t b = 0;
-    if (prev) {
-      ok = spin_tag(ring_slot(slots, l - 1, k), tag_p, b);
-      acc_p += untag(b);
-    }
-    if (ok && last) {
-      ok = spin_tag(ring_slot(slots, l, k), tag_l, b);
-      acc_l += untag(b);
-    } else if (ok && ((nbm[k >> 5] >> (k & 31)) & 1u)) {
-      ok = spin_tag(ring_slot(slots, l, k), tag_l, b);
-    }
+    // both slots' loads in flight together; a slot not yet tagged is then
+    // polled on its own
+    const bool want_l = last || ((nbm[k >> 5] >> (k & 31)) & 1u);
+    const uint64_t* pp = ring_slot(slots, l - 1, k);
+    const uint64_t* pl = ring_slot(slots, l, k);
+    uint64_t bp = prev ? ld_relaxed(pp) : 0ull;
+    uint64_t bl = want_l ? ld_relaxed(pl) : 0ull;
+    if (prev && (bp & 0xffull) != tag_p) ok = spin_tag(pp, tag_p, bp);
+    if (ok && want_l && (bl & 0xffull) != tag_l) ok = spin_tag(pl, tag_l, bl);
+    acc_p += prev ? untag(bp) : 0.0;
+    acc_l += last ? untag(bl) : 0.0;
   }
   if (!ok) atomicOr(s_flag, 1);  // read after poll_sum's barrier
   acc_p = prev ? poll_sum(acc_p, s_poll) : 0.0;
