@@ -790,7 +790,18 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--detail", default="", help="also write every measurement to this JSON file")
+    ap.add_argument("--maps-out", default="",
+                    help="write the process's memory map (/proc/self/maps) to this file at exit, to resolve the "
+                         "addresses of a native stack trace printed after the program ends")
     args = ap.parse_args()
+    if args.maps_out:
+        import atexit
+
+        def _dump_maps(path=args.maps_out):
+            os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+            with open("/proc/self/maps") as src, open(path, "w") as dst:
+                dst.write(src.read())
+        atexit.register(_dump_maps)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it", file=sys.stderr)
         sys.exit(2)
