@@ -91,14 +91,15 @@ def kernel_sources_hash():
 
 
 def load_traffic(name):
-    """HBM traffic per launch from a committed rocprofv3 --pmc summary, or None
-    when the kernels changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary
+    (profiles/traffic.json, one entry per workload), or None when the
+    kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        t = json.load(f)
-    if t.get("sources_hash") != kernel_sources_hash():
+        t = json.load(f).get(name)
+    if not t or t.get("sources_hash") != kernel_sources_hash():
         return None
     return t.get("bytes_per_launch")
 
