@@ -363,6 +363,62 @@ def batched_rollout_gpu(args, torch, vf, scenes, envs_sub, steps):
     return xs, vs
 
 
+def rollout_bench(args, torch, vf, scenes):
+    """The 10x10 cloth dropped 2 cm onto the plane (100 steps) and the 128x128
+    cloth dropped onto its 16 spheres (200 steps, mass damping 5/s) as the
+    rollouts those workloads name: every step assembles A, b and the contacts on the host at the GPU's
+    own state, solves to theta < tol on the GPU and advances x += h v, so the
+    contact set evolves.  Run with W recomputed every step, and with the row
+    sums of W reused (reuse_w) for nine steps in ten.  A step that does not
+    converge (status other than converged) or returns a non-finite iterate
+    ends its rollout, which reports where.  Per rollout: GPU setup and solve
+    time, sweeps, contact counts, host time (assembly and transfers)."""
+    import numpy as np
+    cases = (("cloth10_drop_100_steps", lambda: scenes.cloth_cfg1(args.seed, landing=False), 100),
+             ("cloth128_drop_onto_spheres_200_steps", lambda: scenes.cloth_cfg2_drop(args.seed), 200))
+    out = {}
+    for name, make, steps in cases:
+        res = {}
+        for reuse in (False, True):
+            sc, x, v = make()
+            solve, setup, sweeps, ncs = [], [], [], []
+            host = 0.0
+            failed = None
+            t0 = time.perf_counter()
+            with vf.Solver(sc.n_nodes, int(sc.row_ptr[-1]), sc.n_nodes) as s:
+                vf.vfpi_timing_enable(s.ctx, True)
+                for k in range(steps):
+                    th = time.perf_counter()
+                    p = sc.assemble(x, v)
+                    A, b, Jc, vv, lam, stats = upload(torch, vf, p)
+                    host += time.perf_counter() - th
+                    s.step(A, b, Jc, vv, lam, stats=stats, max_iters=args.rollout_max_iters, tol=args.rollout_tol,
+                           reuse_w=reuse and k % 10 != 0)
+                    a_, c_ = vf.vfpi_timing_read(s.ctx)
+                    st = vf.read_stats(stats)[0]
+                    setup.append(a_)
+                    solve.append(c_)
+                    sweeps.append(st["iters"])
+                    ncs.append(p.n_contacts)
+                    th = time.perf_counter()
+                    v = vv.cpu().numpy().reshape(-1, 3)
+                    host += time.perf_counter() - th
+                    if st["status"] != 0 or not np.all(np.isfinite(v)):
+                        failed = {"step": k, "status": st["status"], "iters": st["iters"], "theta": st["theta"]}
+                        break
+                    th = time.perf_counter()
+                    x = sc.advance(x, v)
+                    host += time.perf_counter() - th
+            res["reuse_w" if reuse else "w_every_step"] = {
+                "gpu_solve_ms": sum(solve), "gpu_setup_ms": sum(setup), "sweeps_total": sum(sweeps),
+                "sweeps_mean": sum(sweeps) / len(sweeps), "sweeps_max": max(sweeps),
+                "contacts_first_last_max": [ncs[0], ncs[-1], max(ncs)], "host_ms": host * 1e3,
+                "wall_ms": (time.perf_counter() - t0) * 1e3, "final_x": x.copy(),
+                "steps_done": len(sweeps), "stopped": failed}
+        out[name] = {"steps": steps, "tol": args.rollout_tol, **res}
+    return out
+
+
 def adjoint_bench(args, torch, vf, scenes):
     """64x64 cloth: one converged step (tol 1e-13) forward with tape and its
     adjoint (kernel times), also with anisotropic friction and with the
@@ -634,6 +690,24 @@ def _env_rollout_oracle(e):
     return xs, vs
 
 
+def _cloth10_rollout_oracle(args_t):
+    """FP64 oracle rollout of the 10x10 cloth drop (the same steps as the
+    GPU's, W recomputed every step)."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    import scenes
+    seed, steps, tol, max_iters = args_t
+    sc, x, v = scenes.cloth_cfg1(seed, landing=False)
+    sw = []
+    with threadpool_limits(1):
+        for _ in range(steps):
+            f = oracle.vfpi(sc.assemble(x, v), max_iters=max_iters, tol=tol)
+            sw.append(f["iters"])
+            v = f["v"].reshape(-1, 3)
+            x = sc.advance(x, v)
+    return x, sw
+
+
 def cpu_baseline(pool, P, p, args, what):
     """The oracle on every allotted host core at once (one single-thread
     process per core, same input): aggregate and per-process throughput."""
@@ -790,6 +864,9 @@ def main():
     ap.add_argument("--scaling-only", action="store_true", help="only the size sweep (for counter runs)")
     ap.add_argument("--batched-variant", type=lambda x: int(x, 0), default=0)
     ap.add_argument("--rollout-steps", type=int, default=100)
+    ap.add_argument("--rollout-tol", type=float, default=1e-6, help="tolerance of the cloth rollouts' steps")
+    ap.add_argument("--rollout-max-iters", type=int, default=2000)
+    ap.add_argument("--no-cloth-rollouts", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--detail", default="", help="also write every measurement to this JSON file")
@@ -811,6 +888,7 @@ def main():
     if args.scaling_only:
         args.no_cpu = args.no_batched = args.no_soft = args.no_adjoint = args.no_context = True
 
+    import numpy as np
     import torch
 
     import scenes
@@ -880,6 +958,28 @@ def main():
         r = plain_bench(args, torch, vf, q, variant=5 | (2 << 8))
         legs["cloth10"] = leg_summary(r, q, "cloth 10x10 landing on a plane, FP64")
         detail["cloth10"] = r
+    if not args.no_soft and not args.no_cloth_rollouts:
+        say("cloth rollouts (10x10 drop, 128x128 drop onto spheres)")
+        orc10 = None
+        if pool is not None:
+            orc10 = pool.apply_async(_cloth10_rollout_oracle,
+                                     ((args.seed, 100, args.rollout_tol, args.rollout_max_iters),))
+        rr = rollout_bench(args, torch, vf, scenes)
+        legs["cloth_rollouts"] = {}
+        for k, r in rr.items():
+            legs["cloth_rollouts"][k] = {"steps": r["steps"], "tol": r["tol"]}
+            for mode in ("w_every_step", "reuse_w"):
+                m = dict(r[mode])
+                m.pop("final_x")
+                legs["cloth_rollouts"][k][mode] = {a: (r3(b_) if isinstance(b_, float) else b_) for a, b_ in m.items()}
+        if orc10 is not None:
+            ox, osw = orc10.get()
+            gx = rr["cloth10_drop_100_steps"]["w_every_step"]["final_x"]
+            legs["cloth_rollouts"]["cloth10_drop_100_steps"]["vs_oracle_rollout"] = {
+                "max_final_position_diff_m": r3(float(np.abs(gx - ox).max()), 3),
+                "oracle_sweeps_total": int(sum(osw))}
+        detail["cloth_rollouts"] = {k: {m: {a: b_ for a, b_ in r[m].items() if a != "final_x"}
+                                        for m in ("w_every_step", "reuse_w")} for k, r in rr.items()}
     if not args.no_context:
         say("convergence runs and extensions")
         detail["context"] = context_bench(args, torch, vf, scenes, p_cl)
