@@ -452,24 +452,34 @@ def adjoint_bench(args, torch, vf, scenes):
         bwd.append(vf.vfpi_timing_read(s.ctx)[1])
         fit, bit = vf.read_stats(st)[0]["iters"], vf.read_stats(g["stats"])[0]["iters"]
 
-    def variant_step(Jc_, **opt):
+    def variant_step(Jc_, s_=s, A_=A, b_=b, tape_=tape, gv_=gv, v0_=p.v0, **opt):
         fw, bw = [], []
         for _ in range(3):
-            v = torch.as_tensor(p.v0, device=dev).clone()
-            _, st_ = s.step(A, b, Jc_, v, tape=tape, max_iters=100000, tol=1e-13, **opt)
-            fw.append(vf.vfpi_timing_read(s.ctx)[1])
-            g_ = s.step_backward(A, Jc_, tape, gv, max_iters=100000, tol=1e-13, want_A=True, **opt)
-            bw.append(vf.vfpi_timing_read(s.ctx)[1])
-        f_, b_ = vf.read_stats(st_)[0], vf.read_stats(g_["stats"])[0]
+            v = torch.as_tensor(v0_, device=dev).clone()
+            _, st_ = s_.step(A_, b_, Jc_, v, tape=tape_, max_iters=100000, tol=1e-13, **opt)
+            fw.append(vf.vfpi_timing_read(s_.ctx)[1])
+            g_ = s_.step_backward(A_, Jc_, tape_, gv_, max_iters=100000, tol=1e-13, want_A=True, **opt)
+            bw.append(vf.vfpi_timing_read(s_.ctx)[1])
+        f_, bs = vf.read_stats(st_)[0], vf.read_stats(g_["stats"])[0]
         return {"step_fwd_ms": sorted(fw)[1], "step_bwd_ms": sorted(bw)[1], "fwd_sweeps": f_["iters"],
-                "bwd_sweeps": b_["iters"], "n_slip": f_["n_slip"],
+                "bwd_sweeps": bs["iters"], "n_slip": f_["n_slip"],
                 "bwd_over_fwd": sorted(bw)[1] / sorted(fw)[1],
-                "converged": bool(f_["status"] == 0 and b_["status"] == 0)}
+                "converged": bool(f_["status"] == 0 and bs["status"] == 0)}
 
     Jc_aniso = vf.contacts_from_arrays(crp, ccol, cval, p.phi, p.mu, device=dev, mu2=0.5 * np.asarray(p.mu))
     variants = {"anisotropic, mu2 = mu/2 (f4)": variant_step(Jc_aniso),
                 "proximal operator (f3)": variant_step(Jc, projection="proximal")}
     vf.vfpi_timing_enable(s.ctx, False)
+    # D-contacts (J_m = [R, -R] on two nodes): two 64x64 cloths meeting in free fall
+    q = scenes.cloth_pair_collision(args.seed, side=64)
+    sq = vf.Solver(q.n_nodes, q.nnzb, q.n_contacts)
+    Aq, bq, Jq, _, _, _ = upload(torch, vf, q)
+    vf.vfpi_timing_enable(sq.ctx, True)
+    variants["D-contacts, two 64x64 cloths (f2)"] = variant_step(
+        Jq, s_=sq, A_=Aq, b_=bq, tape_=sq.tape(q.n_nodes, q.n_contacts),
+        gv_=torch.as_tensor(np.random.default_rng(2).normal(size=q.n), device=dev), v0_=q.v0)
+    variants["D-contacts, two 64x64 cloths (f2)"]["n_contacts"] = q.n_contacts
+    sq.close()
     x0t = torch.as_tensor(x0, device=dev)
     v0t = torch.as_tensor(v0, device=dev)
     target = x0t.clone()
@@ -1053,7 +1063,9 @@ def main():
                            "bwd_over_fwd_rollout": r3(ra["bwd_over_fwd_rollout"]),
                            "rollout_fwd_s": r3(ra["rollout_fwd_s"]), "rollout_fwd_bwd_s": r3(ra["rollout_fwd_bwd_s"]),
                            "aniso_bwd_over_fwd": r3(ra["contact_models"]["anisotropic, mu2 = mu/2 (f4)"]
-                                                    ["bwd_over_fwd"])}
+                                                    ["bwd_over_fwd"]),
+                           "d_contact_bwd_over_fwd": r3(ra["contact_models"]["D-contacts, two 64x64 cloths (f2)"]
+                                                        ["bwd_over_fwd"])}
         detail["adjoint"] = ra
     if not args.no_scaling:
         say("size sweep")

@@ -427,22 +427,28 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint(AdjArgs a) {
   });
 }
 
-// Register-resident adjoint (S-contacts; one pass: every workgroup owns at
-// most NW chunks).  A lane keeps its node's first KC block levels of A and
-// its own g~, t and u in registers for the whole solve; only s = W t goes
-// through memory, written as whole lines through LDS and gathered coherently
-// by the neighbours' products.  The contact term of G^T is formed once, before
-// the iteration: a contact node's 3x3 matrix M = (w_i / gamma) R^T D_P^T R
-// (D_P of the taped branch, for the elliptic cone with its closest-point
-// multiplier solved once), kept in LDS, so a sweep applies t = u - M u with no
-// further reads of the contact record or the tape.  Same sweeps as k_adjoint
-// (the contact term in another rounding order).
+// Register-resident adjoint (one pass: every workgroup owns at most NW
+// chunks).  A lane keeps its node's first KC block levels of A and its own t
+// and u in registers for the whole solve; only s = W t goes through memory,
+// written as whole lines through LDS and gathered coherently by the
+// neighbours' products.  The contact term of G^T is formed once, before the
+// iteration: a contact node keeps P = R^T D_P^T R (D_P of the taped branch,
+// for the elliptic cone with its closest-point multiplier solved once) and
+// two factors in LDS, so a sweep applies t = u - P (a u - c u_p) with no
+// further reads of the contact record or the tape: a = w_i / gamma, c = 0
+// for an S-contact; for a D-contact (J_m = [R, -R]) u_p is the partner
+// node's u of the same sweep, a = w_x / gamma and c = w_p / gamma for node x
+// and its partner p, and the two nodes exchange u through memory in a second
+// grid barrier per sweep.  Same sweeps as k_adjoint (the contact term in
+// another rounding order).
 template <int NW, int KC>
 __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   __shared__ double s_red[NW];
   __shared__ double s_poll[3 * NW];  // see grid_sum
   __shared__ double s_out[NW][192];
-  __shared__ double s_M[NW][9][64];
+  __shared__ double s_M[NW][9][64];   // P = R^T D_P^T R of the lane's contact (0 off contacts)
+  __shared__ double s_ac[NW][2][64];  // factors a, c of t = u - P (a u - c u_p)
+  __shared__ int s_pn[NW][64];        // the partner node of a D-contact (else the node itself)
   __shared__ double s_gw[NW][6][64];  // g~ (3) and W (3) of the lane's node
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
@@ -504,11 +510,21 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       for (int r = 0; r < 3; ++r) w3[r] = a.w[3 * i + r];
 #pragma unroll
     for (int r = 0; r < 3; ++r) s_gw[slot][3 + r][lane] = w3[r];
-    // M = f R^T D_P^T R, f = w_i / gamma (zero off contacts: t = u exactly)
+    // P = R^T D_P^T R and the factors (zero off contacts: t = u exactly)
     double M[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double fa = 0.0, fc = 0.0;
+    int pn = act ? (int)i : 0;
     if (m >= 0) {
       const double* R = a.cpack + kPack * (int64_t)m;
-      const double f = w3[0] / R[11];
+      if (adj_isd(a, m)) {
+        const int64_t pi = a.cpair[2 * (int64_t)m], pj = a.cpair[2 * (int64_t)m + 1];
+        const bool first = pi == i;
+        pn = (int)(first ? pj : pi);
+        fa = w3[0] / R[11];
+        fc = a.w[3 * (int64_t)pn] / R[11];
+      } else {
+        fa = w3[0] / R[11];
+      }
       double Dt[3][3];  // Dt[.][k] = D_P^T e_k
       for (int k = 0; k < 3; ++k) {
         double x[3] = {0.0, 0.0, 0.0}, y[3], dmu, dmu2;
@@ -521,20 +537,28 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
           double acc = 0.0;
           for (int p = 0; p < 3; ++p)
             for (int q = 0; q < 3; ++q) acc += R[3 * p + r] * Dt[p][q] * R[3 * q + c2];
-          M[3 * r + c2] = f * acc;
+          M[3 * r + c2] = acc;
         }
     }
 #pragma unroll
     for (int e = 0; e < 9; ++e) s_M[slot][e][lane] = M[e];
+    s_ac[slot][0][lane] = fa;
+    s_ac[slot][1][lane] = fc;
+    s_pn[slot][lane] = pn;
   }
+  const bool has_d = a.cpair != nullptr;  // the same in every workgroup
   auto W = [&](int r) { return s_gw[slot][3 + r][lane]; };
-  // t = G^T u for this lane's node: u - M u
-  auto gtm = [&](const double u[3], double out[3]) {
+  // t = G^T u for this lane's node: u - P (a u - c u_p)
+  auto gtm = [&](const double u[3], const double up[3], double out[3]) {
     double Mr[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) Mr[e] = s_M[slot][e][lane];
+    const double fa_ = s_ac[slot][0][lane], fc_ = s_ac[slot][1][lane];
+    double z[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) out[r] = u[r] - (Mr[3 * r] * u[0] + Mr[3 * r + 1] * u[1] + Mr[3 * r + 2] * u[2]);
+    for (int r = 0; r < 3; ++r) z[r] = fa_ * u[r] - fc_ * up[r];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) out[r] = u[r] - (Mr[3 * r] * z[0] + Mr[3 * r + 1] * z[1] + Mr[3 * r + 2] * z[2]);
   };
   // y = A x for this lane's row (every thread calls)
   auto spmv = [&](const double* x, double out[3]) {
@@ -567,6 +591,16 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     }
   };
   int seq = 0;
+  // u of the D-contact partner (every thread calls): published in E, a grid
+  // barrier, then read back; for any other node its own u
+  auto partner_u = [&](const double u[3], double up[3]) {
+    const int pn = s_pn[slot][lane];
+    const bool dl = act && pn != (int)i;
+    if (dl)
+      for (int r = 0; r < 3; ++r) stv<true>(a.E + 3 * i + r, u[r]);
+    grid_barrier(a.slots, G, lb, ++seq, s_poll);
+    for (int r = 0; r < 3; ++r) up[r] = dl ? ldv<true>(a.E + 3 * (int64_t)pn + r) : u[r];
+  };
   // phase A: e = J^T Gamma^-1 D_P^T g_lam, p = W e
   double e3[3] = {0.0, 0.0, 0.0};
   if (a.gl) {
@@ -574,7 +608,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       const double* R = a.cpack + kPack * (int64_t)m;
       double x[3] = {a.gl[3 * (int64_t)m], a.gl[3 * (int64_t)m + 1], a.gl[3 * (int64_t)m + 2]}, y[3], dmu, dmu2;
       dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, x, y, &dmu, &dmu2);
-      const double gi = 1.0 / R[11];
+      const double gi = (adj_isd(a, m) && a.cpair[2 * (int64_t)m] != i) ? -1.0 / R[11] : 1.0 / R[11];
       for (int r = 0; r < 3; ++r) e3[r] = (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
     }
     const double p3[3] = {W(0) * e3[0], W(1) * e3[1], W(2) * e3[2]};
@@ -587,9 +621,12 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     double Ap[3] = {0.0, 0.0, 0.0};
     if (a.gl) spmv(a.S[1], Ap);
     double gt[3] = {0.0, 0.0, 0.0};
-    if (act) {
+    if (act)
       for (int r = 0; r < 3; ++r) gt[r] = a.gl ? a.gv[3 * i + r] - e3[r] + Ap[r] : a.gv[3 * i + r];
-      gtm(gt, tt);
+    double gp[3] = {gt[0], gt[1], gt[2]};
+    if (has_d) partner_u(gt, gp);
+    if (act) {
+      gtm(gt, gp, tt);
       for (int r = 0; r < 3; ++r) uu[r] = gt[r];
     }
 #pragma unroll
@@ -605,10 +642,14 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       double As[3];
       spmv(a.S[cur], As);
       double th2 = 0.0;
-      if (act) {
-        double un[3], tn[3];
+      double un[3] = {0.0, 0.0, 0.0};
+      if (act)
         for (int r = 0; r < 3; ++r) un[r] = s_gw[slot][r][lane] + tt[r] - As[r];
-        gtm(un, tn);
+      double up[3] = {un[0], un[1], un[2]};
+      if (has_d) partner_u(un, up);
+      if (act) {
+        double tn[3];
+        gtm(un, up, tn);
         for (int r = 0; r < 3; ++r) {
           const double d = un[r] - uu[r];
           th2 += d * d;
@@ -630,22 +671,37 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     a.stats->n_open = a.stats->n_stick = a.stats->n_slip = a.stats->reserved = 0;
   }
   // final gradients (A_bar reads the solution v of the neighbours from the tape)
+  double uf[3] = {uu[0], uu[1], uu[2]};
+  if (has_d) partner_u(uu, uf);  // u of the partner (every thread calls)
   if (!act) return;
   double q[3] = {uu[0], uu[1], uu[2]};
   if (m >= 0) {
     const double* R = a.cpack + kPack * (int64_t)m;
-    const double wb = W(0);
+    const bool isd = adj_isd(a, m);
+    const bool first = !isd || a.cpair[2 * (int64_t)m] == i;
+    // r = J_m W u + g_lam with J_m = [R] or [R, -R] on nodes (i, j)
+    const double* ui = first ? uu : uf;
+    const double wi = first ? W(0) : a.w[3 * (int64_t)s_pn[slot][lane]];
     double rr[3], y[3], dmu, dmu2;
     for (int k = 0; k < 3; ++k) {
-      rr[k] = R[3 * k] * (wb * uu[0]) + R[3 * k + 1] * (wb * uu[1]) + R[3 * k + 2] * (wb * uu[2]);
+      rr[k] = R[3 * k] * (wi * ui[0]) + R[3 * k + 1] * (wi * ui[1]) + R[3 * k + 2] * (wi * ui[2]);
       if (a.gl) rr[k] += a.gl[3 * (int64_t)m + k];
+    }
+    if (isd) {
+      const double* uj = first ? uf : uu;
+      const double wj = first ? a.w[3 * (int64_t)s_pn[slot][lane]] : W(0);
+      for (int k = 0; k < 3; ++k)
+        rr[k] -= R[3 * k] * (wj * uj[0]) + R[3 * k + 1] * (wj * uj[1]) + R[3 * k + 2] * (wj * uj[2]);
     }
     dp_transpose(a.lamstar + 3 * (int64_t)m, a.branch[m], R, a.proj, rr, y, &dmu, &dmu2);
     const double gi = 1.0 / R[11];
-    for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * gi;
-    a.grad_phi[m] = -y[0] * gi;
-    a.grad_mu[m] = dmu;
-    if (a.grad_mu2) a.grad_mu2[m] = dmu2;
+    const double sg = first ? gi : -gi;
+    for (int r = 0; r < 3; ++r) q[r] -= (R[r] * y[0] + R[3 + r] * y[1] + R[6 + r] * y[2]) * sg;
+    if (first) {
+      a.grad_phi[m] = -y[0] * gi;
+      a.grad_mu[m] = dmu;
+      if (a.grad_mu2) a.grad_mu2[m] = dmu2;
+    }
   }
   double bb[3];
   for (int r = 0; r < 3; ++r) {
@@ -766,9 +822,9 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
 
   const int kind = opts->variant & 0xff;
   const int grid_req = (opts->variant >> 16) & 0xff;
-  // register-resident adjoint: S-contacts, variant 0 or kind 5, one workgroup
-  // per CU at most with the fewest chunk slots that fit
-  if (!aa.cpair && (kind == 0 || kind == 5)) {
+  // register-resident adjoint: variant 0 or kind 5, one workgroup per CU at
+  // most with the fewest chunk slots that fit
+  if (kind == 0 || kind == 5) {
     const int64_t cap = ctx->num_cu < kMaxGridSlots ? ctx->num_cu : kMaxGridSlots;
     int want_nw = (opts->variant >> 8) & 0xff;
     for (int nw : {2, 4, 8}) {

@@ -129,6 +129,29 @@ def test_adjoint_grid_and_single_workgroup_agree():
     say(f"  cloth64 adjoint: fwd {a['fwd_stats']['iters']} bwd {a['bwd_stats']['iters']} sweeps, {errs}")
 
 
+def test_d_contact_adjoint_launches_agree():
+    """D-contacts (two 32x32 cloths meeting, J_m = [R, -R]): the register-
+    resident adjoint (default and 8 chunk slots), the streaming one and one
+    workgroup agree, and the default matches the oracle's adjoint."""
+    p = scenes.cloth_pair_collision(0, side=32)
+    assert p.n_contacts > 100 and (np.asarray(p.c_node_j) >= 0).all()
+    g = np.random.default_rng(5)
+    gv, gl = g.normal(size=p.n), g.normal(size=3 * p.n_contacts)
+    a = gpu_fwd_bwd(p, gv, gl, tol=1e-13)
+    assert a["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
+    assert a["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, a["bwd_stats"]
+    for var in (1, 3, 5 | (8 << 8)):
+        b = gpu_fwd_bwd(p, gv, gl, tol=1e-13, variant=var)
+        say(f"  D adjoint variant {var:#x}: {b['bwd_stats']['iters']} sweeps (default {a['bwd_stats']['iters']})")
+        assert abs(b["bwd_stats"]["iters"] - a["bwd_stats"]["iters"]) <= 1
+        for k in ("b", "A", "phi", "mu"):
+            gate(a[k], b[k], 1e-10, f"D variant {var:#x} grad {k}")
+    fwd = oracle.vfpi(p, max_iters=200000, tol=1e-13)
+    ref = oracle_adjoint(p, fwd, gv, gl, tol=1e-14)
+    errs = {k: gate(a[k], ref[k], 1e-6, f"cloth pair grad {k}") for k in ("b", "A", "phi", "mu")}
+    say(f"  cloth pair D adjoint: {p.n_contacts} contacts, bwd {a['bwd_stats']['iters']} sweeps, {errs}")
+
+
 def _aniso_cases():
     for name, p in list(_cases())[1:]:
         p.mu2 = np.asarray(p.mu) * np.random.default_rng(p.n_nodes).uniform(0.3, 1.8, size=p.n_contacts)
