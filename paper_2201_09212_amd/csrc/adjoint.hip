@@ -216,7 +216,7 @@ VFPI_DEV void arow_bsr(const AdjArgs& a, const double* y, int64_t x, double out[
     const int64_t c = a.col_idx[k];
     const double* B = a.val + 9 * k;
     const double y0 = ldv<true>(y + 3 * c), y1 = ldv<true>(y + 3 * c + 1), y2 = ldv<true>(y + 3 * c + 2);
-    for (int r = 0; r < 3; ++r) out[r] += B[3 * r] * y0 + B[3 * r + 1] * y1 + B[3 * r + 2] * y2;
+    for (int r = 0; r < 3; ++r) out[r] += dot3(B[3 * r], B[3 * r + 1], B[3 * r + 2], y0, y1, y2);
   }
 }
 
@@ -573,9 +573,9 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
     out[0] = out[1] = out[2] = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      out[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
-      out[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
-      out[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
+      out[0] += dot3(av[k][0], av[k][1], av[k][2], xs[k][0], xs[k][1], xs[k][2]);
+      out[1] += dot3(av[k][3], av[k][4], av[k][5], xs[k][0], xs[k][1], xs[k][2]);
+      out[2] += dot3(av[k][6], av[k][7], av[k][8], xs[k][0], xs[k][1], xs[k][2]);
     }
     spmv_rows3_from<double, true, (NW >= 8 ? 2 : 1)>(a.scol, a.sval, x, base, nk, lane, KC, off_tail, out);
   };

@@ -66,6 +66,20 @@ VFPI_DEV void stv(T* p, T x) {
     *p = x;
 }
 
+// One row of a 3x3 block times x.  FP64: in a fixed rounding order, with
+// explicit fused multiply-adds, fma(a2, x2, fma(a1, x1, a0 x0)), so that
+// every kernel and instance rounds the product alike, whatever the compiler
+// would contract on its own (which can depend on how the operands were
+// produced).  FP32 (the batched form): as the compiler contracts it.
+template <class T>
+VFPI_DEV T dot3(T a0, T a1, T a2, T x0, T x1, T x2) {
+  return a0 * x0 + a1 * x1 + a2 * x2;
+}
+template <>
+VFPI_DEV double dot3<double>(double a0, double a1, double a2, double x0, double x1, double x2) {
+  return __builtin_fma(a2, x2, __builtin_fma(a1, x1, a0 * x0));
+}
+
 template <class T>
 VFPI_DEV bool finite(T x) { return __builtin_isfinite(x); }
 
@@ -252,9 +266,9 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool has = k0 + u < nk;
-        const T y0 = acc[0] + (a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2]);
-        const T y1 = acc[1] + (a[u][3] * xs[u][0] + a[u][4] * xs[u][1] + a[u][5] * xs[u][2]);
-        const T y2 = acc[2] + (a[u][6] * xs[u][0] + a[u][7] * xs[u][1] + a[u][8] * xs[u][2]);
+        const T y0 = acc[0] + dot3(a[u][0], a[u][1], a[u][2], xs[u][0], xs[u][1], xs[u][2]);
+        const T y1 = acc[1] + dot3(a[u][3], a[u][4], a[u][5], xs[u][0], xs[u][1], xs[u][2]);
+        const T y2 = acc[2] + dot3(a[u][6], a[u][7], a[u][8], xs[u][0], xs[u][1], xs[u][2]);
         acc[0] = has ? y0 : acc[0];
         acc[1] = has ? y1 : acc[1];
         acc[2] = has ? y2 : acc[2];
@@ -343,7 +357,7 @@ VFPI_DEV T spmv_row1(const int32_t* __restrict__ scol, const T* __restrict__ sva
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (k0 + u < nk) acc += a[u][0] * xs[u][0] + a[u][1] * xs[u][1] + a[u][2] * xs[u][2];
+      if (k0 + u < nk) acc += dot3(a[u][0], a[u][1], a[u][2], xs[u][0], xs[u][1], xs[u][2]);
   }
   return acc;
 }

@@ -493,15 +493,32 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       xs[k][1] = ldv<COH>(xp + 1);
       xs[k][2] = ldv<COH>(xp + 2);
     }
+    // up to four LDS levels: their gathers go out with the register levels'
+    // (one round trip for both); more would cost the registers of A's levels
+    constexpr bool EL = KL > 0 && KL <= 4;
+    double xe[EL ? KL : 1][3];
+    if constexpr (EL) {
+      int ce[KL];
+#pragma unroll
+      for (int k = 0; k < KL; ++k) ce[k] = s_cl[slot][k][lane];
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const double* xp = vcur + 3 * (int64_t)ce[k];
+        xe[k][0] = ldv<COH>(xp);
+        xe[k][1] = ldv<COH>(xp + 1);
+        xe[k][2] = ldv<COH>(xp + 2);
+      }
+    }
     double Av[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      Av[0] += av[k][0] * xs[k][0] + av[k][1] * xs[k][1] + av[k][2] * xs[k][2];
-      Av[1] += av[k][3] * xs[k][0] + av[k][4] * xs[k][1] + av[k][5] * xs[k][2];
-      Av[2] += av[k][6] * xs[k][0] + av[k][7] * xs[k][1] + av[k][8] * xs[k][2];
+      Av[0] += dot3(av[k][0], av[k][1], av[k][2], xs[k][0], xs[k][1], xs[k][2]);
+      Av[1] += dot3(av[k][3], av[k][4], av[k][5], xs[k][0], xs[k][1], xs[k][2]);
+      Av[2] += dot3(av[k][6], av[k][7], av[k][8], xs[k][0], xs[k][1], xs[k][2]);
     }
-    // LDS levels, two at a time (both gathers in flight before the products);
-    // levels a row lacks hold zero blocks, so there is no branch here
+    // LDS levels, two at a time (both gathers in flight before the products,
+    // unless gathered above); levels a row lacks hold zero blocks, so there
+    // is no branch here
 #pragma unroll
     for (int k0 = 0; k0 < KL; k0 += 2) {
       double xl[2][3];
@@ -509,10 +526,15 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       for (int u = 0; u < 2; ++u) {
         const int k = k0 + u;
         if (k < KL) {
-          const double* xp = vcur + 3 * (int64_t)s_cl[slot][k][lane];
-          xl[u][0] = ldv<COH>(xp);
-          xl[u][1] = ldv<COH>(xp + 1);
-          xl[u][2] = ldv<COH>(xp + 2);
+          if constexpr (EL) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) xl[u][r] = xe[k][r];
+          } else {
+            const double* xp = vcur + 3 * (int64_t)s_cl[slot][k][lane];
+            xl[u][0] = ldv<COH>(xp);
+            xl[u][1] = ldv<COH>(xp + 1);
+            xl[u][2] = ldv<COH>(xp + 2);
+          }
         }
       }
 #pragma unroll
@@ -526,7 +548,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int r = 0; r < 3; ++r)
-            Av[r] += al[3 * r] * xl[u][0] + al[3 * r + 1] * xl[u][1] + al[3 * r + 2] * xl[u][2];
+            Av[r] += dot3(al[3 * r], al[3 * r + 1], al[3 * r + 2], xl[u][0], xl[u][1], xl[u][2]);
         }
       }
     }

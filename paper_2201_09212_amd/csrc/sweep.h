@@ -103,7 +103,7 @@ VFPI_DEV void vstar_bsr(const SweepData<T>& a, const T* __restrict__ vcur, const
     const T* B = a.val + 9 * k;
     const T y0 = ldv<COH>(vcur + 3 * c), y1 = ldv<COH>(vcur + 3 * c + 1), y2 = ldv<COH>(vcur + 3 * c + 2);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) acc[r] += B[3 * r] * y0 + B[3 * r + 1] * y1 + B[3 * r + 2] * y2;
+    for (int r = 0; r < 3; ++r) acc[r] += dot3(B[3 * r], B[3 * r + 1], B[3 * r + 2], y0, y1, y2);
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
