@@ -540,23 +540,28 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
           M[3 * r + c2] = acc;
         }
     }
+    // without D-contacts the factor goes into M: t = u - M u, M = (w / gamma) P
+    const bool sonly = a.cpair == nullptr;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) s_M[slot][e][lane] = M[e];
+    for (int e = 0; e < 9; ++e) s_M[slot][e][lane] = sonly ? fa * M[e] : M[e];
     s_ac[slot][0][lane] = fa;
     s_ac[slot][1][lane] = fc;
     s_pn[slot][lane] = pn;
   }
   const bool has_d = a.cpair != nullptr;  // the same in every workgroup
   auto W = [&](int r) { return s_gw[slot][3 + r][lane]; };
-  // t = G^T u for this lane's node: u - P (a u - c u_p)
+  // t = G^T u for this lane's node: u - P (a u - c u_p); without D-contacts
+  // u - M u (the factor a is in M)
   auto gtm = [&](const double u[3], const double up[3], double out[3]) {
     double Mr[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) Mr[e] = s_M[slot][e][lane];
-    const double fa_ = s_ac[slot][0][lane], fc_ = s_ac[slot][1][lane];
-    double z[3];
+    double z[3] = {u[0], u[1], u[2]};
+    if (has_d) {
+      const double fa_ = s_ac[slot][0][lane], fc_ = s_ac[slot][1][lane];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) z[r] = fa_ * u[r] - fc_ * up[r];
+      for (int r = 0; r < 3; ++r) z[r] = fa_ * u[r] - fc_ * up[r];
+    }
 #pragma unroll
     for (int r = 0; r < 3; ++r) out[r] = u[r] - (Mr[3 * r] * z[0] + Mr[3 * r + 1] * z[1] + Mr[3 * r + 2] * z[2]);
   };
