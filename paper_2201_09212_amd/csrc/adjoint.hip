@@ -497,8 +497,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       const int pos = lanes_below(mk, lane);
       const int64_t q = base + off;
       col[k] = a.scol[q + pos];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) av[k][e] = a.sval[9 * q + (int64_t)e * ck + pos];
+      load_sblock(a.sval, q, ck, pos, av[k]);
     }
     off += ck;
   }
@@ -569,12 +568,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
   auto spmv = [&](const double* x, double out[3]) {
     double xs[KC][3];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const double* xp = x + 3 * (int64_t)col[k];
-      xs[k][0] = ldv<true>(xp);
-      xs[k][1] = ldv<true>(xp + 1);
-      xs[k][2] = ldv<true>(xp + 2);
-    }
+    for (int k = 0; k < KC; ++k) ldv3<true>(x, col[k], xs[k]);
     out[0] = out[1] = out[2] = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {

@@ -80,6 +80,65 @@ VFPI_DEV double dot3<double>(double a0, double a1, double a2, double x0, double 
   return __builtin_fma(a2, x2, __builtin_fma(a1, x1, a0 * x0));
 }
 
+// Chunk-interleaved copy of A: the blocks of level k of a chunk (ck of them,
+// one per row that has a k-th block, in lane order) sit at block offset q.
+// Position of entry e (row-major, 0..8) of the block of lane position pos.
+// FP64: entries (0,1), (2,3), (4,5), (6,7) as 16-byte pairs, each pair for
+// all ck lanes in lane order, then entry 8 for all lanes, so that a lane
+// reads its block with four 16-byte loads and one 8-byte load (each load
+// instruction reading one contiguous run over the lanes).  FP32: entry-major
+// (entry e for all lanes, then e + 1).
+template <class T>
+VFPI_DEV int64_t sval_at(int64_t q, int ck, int pos, int e) {
+  if constexpr (sizeof(T) == 8)
+    return 9 * q + (e < 8 ? 2 * (int64_t)ck * (e >> 1) + 2 * pos + (e & 1) : 8 * (int64_t)ck + pos);
+  else
+    return 9 * q + (int64_t)e * ck + pos;
+}
+
+// One block of the interleaved copy into registers (see sval_at).
+VFPI_DEV void load_sblock(const double* __restrict__ sval, int64_t q, int ck, int pos, double a[9]) {
+  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));  // 72 q bytes: 8-byte aligned
+  const double* bp = sval + 9 * q + 2 * pos;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const d2 t = *reinterpret_cast<const d2*>(bp + 2 * (int64_t)ck * p);
+    a[2 * p] = t.x;
+    a[2 * p + 1] = t.y;
+  }
+  a[8] = sval[9 * q + 8 * (int64_t)ck + pos];
+}
+VFPI_DEV void load_sblock(const float* __restrict__ sval, int64_t q, int ck, int pos, float a[9]) {
+  const float* ap = sval + 9 * q + pos;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) a[e] = ap[(int64_t)e * ck];
+}
+
+// The three components of node c of an FP64 iterate x (24 bytes) in two
+// loads of 16 and 8 bytes instead of three.  COH: with the agent-coherent
+// cache policy (the bit the relaxed agent-scope atomic loads set), through a
+// raw buffer resource over x; no atomicity is needed, since the values were
+// published before the barrier that precedes the gather.
+typedef unsigned int vfpi_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int vfpi_u32x2 __attribute__((ext_vector_type(2)));
+template <bool COH>
+VFPI_DEV void ldv3(const double* __restrict__ x, int64_t c, double out[3]) {
+  if constexpr (COH) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(x), 0, 0x7fffffff, 0x00020000);
+    const uint32_t off = 24u * (uint32_t)c;
+    const vfpi_u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 1 << 4);
+    const vfpi_u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 16u, 0, 1 << 4);
+    out[0] = __builtin_bit_cast(double, (uint64_t)a[0] | ((uint64_t)a[1] << 32));
+    out[1] = __builtin_bit_cast(double, (uint64_t)a[2] | ((uint64_t)a[3] << 32));
+    out[2] = __builtin_bit_cast(double, b);
+  } else {
+    out[0] = x[3 * c];
+    out[1] = x[3 * c + 1];
+    out[2] = x[3 * c + 2];
+  }
+}
+
 template <class T>
 VFPI_DEV bool finite(T x) { return __builtin_isfinite(x); }
 
@@ -250,19 +309,10 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
         c[u] = scol[q[u] + pos[u]];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const T* ap = sval + 9 * q[u] + pos[u];
-#pragma unroll
-        for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cu[u]];
-      }
+      for (int u = 0; u < U; ++u) load_sblock(sval, q[u], cu[u], pos[u], a[u]);
       T xs[U][3];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const T* xp = x + 3 * (int64_t)c[u];
-        xs[u][0] = ldv<COH>(xp);
-        xs[u][1] = ldv<COH>(xp + 1);
-        xs[u][2] = ldv<COH>(xp + 2);
-      }
+      for (int u = 0; u < U; ++u) ldv3<COH>(x, c[u], xs[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool has = k0 + u < nk;
@@ -284,9 +334,7 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
           const int pos = lanes_below(m[u], lane);
           const int64_t q = base + offk[u];
           c[u] = scol[q + pos];
-          const T* ap = sval + 9 * q + pos;
-#pragma unroll
-          for (int e = 0; e < 9; ++e) a[u][e] = ap[(int64_t)e * cnt[u]];
+          load_sblock(sval, q, cnt[u], pos, a[u]);
         }
       }
       T xs[U][3];
@@ -339,10 +387,8 @@ VFPI_DEV T spmv_row1(const int32_t* __restrict__ scol, const T* __restrict__ sva
         const int pos = lanes_below(m[u], lane);
         const int64_t q = base + offk[u];
         c[u] = scol[q + pos];
-        const T* ap = sval + 9 * q + (int64_t)3 * r * cnt[u] + pos;
-        a[u][0] = ap[0];
-        a[u][1] = ap[cnt[u]];
-        a[u][2] = ap[2 * (int64_t)cnt[u]];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a[u][j] = sval[sval_at<T>(q, cnt[u], pos, 3 * r + j)];
       }
     }
     T xs[U][3];

@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   __shared__ double s_bw[NW][6][64];      // b (3), W (3)
   __shared__ double s_cr[NW][kPack][64];  // contact record of the lane's node
   __shared__ double s_lam[NW][6][64];     // lambda, lambda* of the last sweep
-  __shared__ double s_al[KL > 0 ? NW : 1][KL > 0 ? KL : 1][9][64];  // levels KC..KC+KL-1
+  __shared__ double s_al[KL > 0 ? NW : 1][KL > 0 ? KL : 1][9][64];
   __shared__ int s_cl[KL > 0 ? NW : 1][KL > 0 ? KL : 1][64];
   // LAG (S-contacts, no Chebyshev, no BB, more than one workgroup): the stop
   // test of sweep l is taken after sweep l + 1, and between sweeps a
@@ -413,8 +413,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       const int pos = lanes_below(m, lane);
       const int64_t q = base + off;
       col[k] = d.scol[q + pos];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) av[k][e] = d.sval[9 * q + (int64_t)e * ck + pos];
+      load_sblock(d.sval, q, ck, pos, av[k]);
     }
     off += ck;
   }
@@ -427,7 +426,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       const int64_t q = base + off;
       s_cl[slot][k][lane] = d.scol[q + pos];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) s_al[slot][k][e][lane] = d.sval[9 * q + (int64_t)e * ck + pos];
+      for (int e = 0; e < 9; ++e) s_al[slot][k][e][lane] = d.sval[sval_at<double>(q, ck, pos, e)];
     } else {
       // a zero block on a valid column: the sweep's LDS levels then run
       // without branches (adding the exact zero leaves A v unchanged)
@@ -487,12 +486,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     const double nu = CH ? ch.next_nu(l) : 1.0;
     double xs[KC][3];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const double* xp = vcur + 3 * (int64_t)col[k];
-      xs[k][0] = ldv<COH>(xp);
-      xs[k][1] = ldv<COH>(xp + 1);
-      xs[k][2] = ldv<COH>(xp + 2);
-    }
+    for (int k = 0; k < KC; ++k) ldv3<COH>(vcur, col[k], xs[k]);
     // up to four LDS levels: their gathers go out with the register levels'
     // (one round trip for both); more would cost the registers of A's levels
     constexpr bool EL = KL > 0 && KL <= 4;
@@ -502,12 +496,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
       for (int k = 0; k < KL; ++k) ce[k] = s_cl[slot][k][lane];
 #pragma unroll
-      for (int k = 0; k < KL; ++k) {
-        const double* xp = vcur + 3 * (int64_t)ce[k];
-        xe[k][0] = ldv<COH>(xp);
-        xe[k][1] = ldv<COH>(xp + 1);
-        xe[k][2] = ldv<COH>(xp + 2);
-      }
+      for (int k = 0; k < KL; ++k) ldv3<COH>(vcur, ce[k], xe[k]);
     }
     double Av[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -530,10 +519,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
 #pragma unroll
             for (int r = 0; r < 3; ++r) xl[u][r] = xe[k][r];
           } else {
-            const double* xp = vcur + 3 * (int64_t)s_cl[slot][k][lane];
-            xl[u][0] = ldv<COH>(xp);
-            xl[u][1] = ldv<COH>(xp + 1);
-            xl[u][2] = ldv<COH>(xp + 2);
+            ldv3<COH>(vcur, s_cl[slot][k][lane], xl[u]);
           }
         }
       }
@@ -541,7 +527,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       for (int u = 0; u < 2; ++u) {
         const int k = k0 + u;
         if (k < KL) {
-          // all nine LDS reads of the block issue before its products
+          // all five LDS reads of the block issue before its products
           double al[9];
 #pragma unroll
           for (int e = 0; e < 9; ++e) al[e] = s_al[slot][k][e][lane];

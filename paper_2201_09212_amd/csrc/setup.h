@@ -186,7 +186,7 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
         scol[q + pos] = (int32_t)c;
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-          sval[9 * q + (int64_t)e * c_ + pos] = x[u][e];
+          sval[sval_at<T>(q, c_, pos, e)] = x[u][e];
           fin &= finite(x[u][e]);
         }
 #pragma unroll
