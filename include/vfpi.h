@@ -265,7 +265,7 @@ int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc
  * one copy per GPU, held from the first call on that GPU until the process
  * ends.  The call allocates and frees nothing.  The caller still passes every
  * input and output (device pointers, as for vfpi_step); the workspace takes
- *   76 nnzb + 316 N + 112 n_c + 1,098,240 bytes
+ *   76 nnzb + 316 N + 112 n_c + 1,147,392 bytes
  * (each of its 14 parts rounded up to 256 bytes), which must fit the array:
  * about 29,000 nodes of a cloth with 9 blocks per row and a contact on every
  * node (about 32,000 without contacts).  Every call on one GPU

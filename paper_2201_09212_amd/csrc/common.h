@@ -30,12 +30,13 @@ constexpr int kMaxGridSlots = 1024;  // workgroups of a persistent launch (slots
 // the residual / barrier (rings 0-1 for the synchronous reduction, 0-3 for the
 // lagged one), each slot alone in kSlotPad words (256 bytes) so that the
 // workgroups polling one slot do not contend with those polling its
-// neighbours; region 1 = [2][3][kMaxGridSlots] for the three dot products of
-// the Barzilai-Borwein step size.
+// neighbours; region 1 = [2][3][kMaxGridSlots] slots of two words for the
+// three dot products of the Barzilai-Borwein step size.  A slot's value takes
+// two words (see publish in gridsync.h).
 constexpr int kSlotPad = 32;
 constexpr int kSlotRings = 4;
 constexpr int kBBSlotOffset = kSlotRings * kMaxGridSlots * kSlotPad;
-constexpr int kSlotWords = kBBSlotOffset + 6 * kMaxGridSlots;
+constexpr int kSlotWords = kBBSlotOffset + 12 * kMaxGridSlots;
 
 VFPI_DEV uint64_t ballot(bool p) { return __ballot(p); }
 

@@ -18,8 +18,11 @@ __global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t*
   const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i < n_nodes; i += stride) cmap[i] = -1;
-  for (int64_t i = i0; i < kSlotRings * kMaxGridSlots; i += stride) slots[i * kSlotPad] = 0ull;  // region 0
-  for (int64_t i = i0; i < 6 * kMaxGridSlots; i += stride) slots[kBBSlotOffset + i] = 0ull;
+  for (int64_t i = i0; i < kSlotRings * kMaxGridSlots; i += stride) {  // region 0: both words of a slot
+    slots[i * kSlotPad] = 0ull;
+    slots[i * kSlotPad + 1] = 0ull;
+  }
+  for (int64_t i = i0; i < 12 * kMaxGridSlots; i += stride) slots[kBBSlotOffset + i] = 0ull;
   if (i0 == 0) {
     flags[0] = 0;
     for (int k = 0; k < kSyncWords; ++k) sync[k] = 0u;

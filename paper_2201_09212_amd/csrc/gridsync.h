@@ -8,13 +8,12 @@
 //
 // Barrier + residual reduction without read-modify-write atomics: for its
 // k-th synchronization a workgroup first drains its own stores, then
-// publishes its partial sum in slot[k & 1][lb] (one slot per 256 bytes) with
-// a tag derived from k in the 8 low mantissa bits (the partial keeps 44
-// significant bits).  Every
-// workgroup polls all G slots of that parity (one slot per thread, in
-// parallel) until each carries the tag, and sums them in slot order: every
-// workgroup gets the same bits, hence the same convergence decision, without
-// a broadcast step.  Double-buffering by parity is enough: a workgroup can
+// publishes its partial sum in slot[k & 1][lb] (one slot per 256 bytes),
+// tagged with a number derived from k (publish below: the whole FP64 value
+// and the tag in two words).  Every workgroup polls all G slots of that
+// parity (one slot per thread, in parallel) until each carries the tag, and
+// sums them in slot order: every workgroup gets the same bits, hence the same
+// convergence decision, without a broadcast step.  Double-buffering by parity is enough: a workgroup can
 // only overwrite a slot of parity k & 1 at synchronization k + 2, after every
 // workgroup has published for k + 1, i.e. finished polling for k.  Slots
 // start at tag 0, which no synchronization uses.
@@ -41,10 +40,30 @@ VFPI_DEV void drain() {
 
 VFPI_DEV unsigned sync_tag(int seq) { return (unsigned)(seq % 255) + 1u; }
 
-VFPI_DEV uint64_t tagged(double x, unsigned tag) {
-  return (__builtin_bit_cast(uint64_t, x) & ~0xffull) | tag;
+// A partial travels as two tagged 8-byte words: the double's upper 56 bits
+// with the tag in the low byte, and its low byte moved up by 8 bits with the
+// same tag.  Each word is a single-copy atomic store, so a reader that finds
+// the tag in both words holds the whole FP64 value of one publication.
+VFPI_DEV void publish(uint64_t* p, double x, unsigned tag) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  st_relaxed<uint64_t>(p, (b & ~0xffull) | tag);
+  st_relaxed<uint64_t>(p + 1, ((b & 0xffull) << 8) | tag);
 }
-VFPI_DEV double untag(uint64_t b) { return __builtin_bit_cast(double, b & ~0xffull); }
+VFPI_DEV bool tagged_both(uint64_t w0, uint64_t w1, unsigned tag) {
+  return ((w0 & 0xffull) == tag) & ((w1 & 0xffull) == tag);
+}
+VFPI_DEV double joined(uint64_t w0, uint64_t w1) {
+  return __builtin_bit_cast(double, (w0 & ~0xffull) | ((w1 >> 8) & 0xffull));
+}
+// Poll one slot (both words) until it carries `tag`; the words in w0, w1.
+VFPI_DEV void poll_slot(const uint64_t* p, unsigned tag, uint64_t& w0, uint64_t& w1) {
+  for (;;) {
+    w0 = ld_relaxed(p);
+    w1 = ld_relaxed(p + 1);
+    if (tagged_both(w0, w1, tag)) return;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
 
 // Sum over the workgroup of the polled slots with one workgroup barrier:
 // wave sums (DPP) go to red[0, nw) and every thread adds them in wave order,
@@ -71,19 +90,20 @@ VFPI_DEV double grid_sum(uint64_t* slots, int G, int lb, int seq, double x, doub
   uint64_t* sl = slots + (seq & 1) * (int64_t)kMaxGridSlots * kSlotPad;
   drain();
   __syncthreads();
-  if (threadIdx.x == 0) st_relaxed(sl + (int64_t)lb * kSlotPad, tagged(x, tag));
+  if (threadIdx.x == 0) publish(sl + (int64_t)lb * kSlotPad, x, tag);
   double acc = 0.0;
   for (int k = threadIdx.x; k < G; k += blockDim.x) {
-    uint64_t b;
-    while (((b = ld_relaxed(sl + (int64_t)k * kSlotPad)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
-    acc += untag(b);
+    uint64_t w0, w1;
+    poll_slot(sl + (int64_t)k * kSlotPad, tag, w0, w1);
+    acc += joined(w0, w1);
   }
   return poll_sum(acc, s_poll);
 }
 
 // Three partials at once (valid in every thread of the workgroup), in the slot
-// region `reg` = [2][3][kMaxGridSlots] with its own sequence numbers; the
-// same tagging and double-buffering argument as grid_sum applies per region.
+// region `reg` = [2][3][kMaxGridSlots] slots of two words with its own
+// sequence numbers; the same tagging and double-buffering argument as
+// grid_sum applies per region.
 // Returns the fixed-order sums in x, in every thread.
 VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], double* s_red, double* s_poll) {
   if (G == 1) {
@@ -94,20 +114,20 @@ VFPI_DEV void grid_sum3(uint64_t* reg, int G, int lb, int seq, double x[3], doub
 #pragma unroll
   for (int q = 0; q < 3; ++q) x[q] = block_sum(x[q], s_red);
   const unsigned tag = sync_tag(seq);
-  uint64_t* sl = reg + (seq & 1) * 3 * (int64_t)kMaxGridSlots;
+  uint64_t* sl = reg + (seq & 1) * 6 * (int64_t)kMaxGridSlots;
   drain();
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) st_relaxed(sl + q * kMaxGridSlots + lb, tagged(x[q], tag));
+    for (int q = 0; q < 3; ++q) publish(sl + 2 * ((int64_t)q * kMaxGridSlots + lb), x[q], tag);
   }
   double acc[3] = {0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < G; k += blockDim.x) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      uint64_t b;
-      while (((b = ld_relaxed(sl + q * kMaxGridSlots + k)) & 0xffull) != tag) __builtin_amdgcn_s_sleep(1);
-      acc[q] += untag(b);
+      uint64_t w0, w1;
+      poll_slot(sl + 2 * ((int64_t)q * kMaxGridSlots + k), tag, w0, w1);
+      acc[q] += joined(w0, w1);
     }
   }
   const int nw = (blockDim.x + 63) >> 6;
@@ -170,11 +190,13 @@ VFPI_DEV uint64_t* ring_slot(uint64_t* slots, int l, int k) {
   return slots + ((int64_t)(l & (kSlotRings - 1)) * kMaxGridSlots + k) * kSlotPad;
 }
 
-// Poll one slot until it carries `tag`; false on timeout.
-VFPI_DEV bool spin_tag(const uint64_t* p, unsigned tag, uint64_t& b) {
+// Poll one slot until it carries `tag` (both words, or only the first when
+// the value is not wanted); false on timeout.
+VFPI_DEV bool spin_tag(const uint64_t* p, unsigned tag, uint64_t& w0, uint64_t& w1, bool both) {
   for (int n = 0; n < kSpinLimit; ++n) {
-    b = ld_relaxed(p);
-    if ((b & 0xffull) == tag) return true;
+    w0 = ld_relaxed(p);
+    w1 = both ? ld_relaxed(p + 1) : (uint64_t)tag;
+    if (tagged_both(w0, w1, tag)) return true;
     __builtin_amdgcn_s_sleep(1);
   }
   return false;
@@ -197,7 +219,7 @@ VFPI_DEV LagResult lag_sync(uint64_t* slots, int G, int lb, int l, double th2, i
   if (threadIdx.x == 0) *s_flag = 0;
   drain();
   __syncthreads();
-  if (threadIdx.x == 0) st_relaxed(ring_slot(slots, l, lb), tagged(th2, tag_l));
+  if (threadIdx.x == 0) publish(ring_slot(slots, l, lb), th2, tag_l);
   const bool last = l >= max_iters;
   const bool prev = !fixed && l >= 2;
   double acc_p = 0.0, acc_l = 0.0;
@@ -208,12 +230,14 @@ VFPI_DEV LagResult lag_sync(uint64_t* slots, int G, int lb, int l, double th2, i
     const bool want_l = last || ((nbm[k >> 5] >> (k & 31)) & 1u);
     const uint64_t* pp = ring_slot(slots, l - 1, k);
     const uint64_t* pl = ring_slot(slots, l, k);
-    uint64_t bp = prev ? ld_relaxed(pp) : 0ull;
-    uint64_t bl = want_l ? ld_relaxed(pl) : 0ull;
-    if (prev && (bp & 0xffull) != tag_p) ok = spin_tag(pp, tag_p, bp);
-    if (ok && want_l && (bl & 0xffull) != tag_l) ok = spin_tag(pl, tag_l, bl);
-    acc_p += prev ? untag(bp) : 0.0;
-    acc_l += last ? untag(bl) : 0.0;
+    // (a neighbour's slot of sweep l is only waited for, its value unused
+    // before the last sweep: its first word, which carries the tag, suffices)
+    uint64_t bp0 = prev ? ld_relaxed(pp) : 0ull, bp1 = prev ? ld_relaxed(pp + 1) : 0ull;
+    uint64_t bl0 = want_l ? ld_relaxed(pl) : 0ull, bl1 = last ? ld_relaxed(pl + 1) : tag_l;
+    if (prev && !tagged_both(bp0, bp1, tag_p)) ok = spin_tag(pp, tag_p, bp0, bp1, true);
+    if (ok && want_l && !tagged_both(bl0, bl1, tag_l)) ok = spin_tag(pl, tag_l, bl0, bl1, last);
+    acc_p += prev ? joined(bp0, bp1) : 0.0;
+    acc_l += last ? joined(bl0, bl1) : 0.0;
   }
   if (!ok) atomicOr(s_flag, 1);  // read after poll_sum's barrier
   acc_p = prev ? poll_sum(acc_p, s_poll) : 0.0;
