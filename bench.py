@@ -893,7 +893,7 @@ def main():
                 dst.write(src.read())
         atexit.register(_dump_maps)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
     if args.scaling_only:
         args.no_cpu = args.no_batched = args.no_soft = args.no_adjoint = args.no_context = True

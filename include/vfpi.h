@@ -50,7 +50,7 @@ extern "C" {
 #define VFPI_E_SHAPE        -2  /* inconsistent sizes (negative, n_c > N, ...)  */
 #define VFPI_E_OPTS         -3  /* invalid option value                         */
 #define VFPI_E_CAPACITY     -4  /* larger than the context was created for     */
-#define VFPI_E_UNSUPPORTED  -5  /* valid input this build does not solve       */
+#define VFPI_E_UNSUPPORTED  -5  /* valid input the library does not solve      */
 #define VFPI_E_HIP          -6  /* a HIP runtime call failed                    */
 #define VFPI_E_NO_TAPE      -7  /* backward without a forward tape              */
 
