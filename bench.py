@@ -72,11 +72,13 @@ def kernel_sources_hash():
     backward (adjoint.hip) and the virtual-node builder (vnode.hip) are
     included after those kernels in the one translation unit and define
     nothing they use, so they are left out; so is the allocation-free entry
-    point (noalloc.hip, last in that unit), which only calls vfpi_step."""
+    point (noalloc.hip, last in that unit), which only calls vfpi_step, and
+    the host-side context and error-string code (api.hip), which holds no
+    device code."""
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2201_09212_amd", "csrc")
-    skip = ("adjoint.hip", "vnode.hip", "noalloc.hip")
+    skip = ("adjoint.hip", "vnode.hip", "noalloc.hip", "api.hip")
     for f in sorted(os.listdir(csrc)):
         if f in skip:
             continue
