@@ -115,7 +115,7 @@ extern "C" const char* vfpi_error_string(int code) {
     case VFPI_E_SHAPE: return "inconsistent sizes";
     case VFPI_E_OPTS: return "invalid option";
     case VFPI_E_CAPACITY: return "problem larger than the context capacity";
-    case VFPI_E_UNSUPPORTED: return "valid input form that the library does not solve";
+    case VFPI_E_UNSUPPORTED: return "input form not supported by the library";
     case VFPI_E_HIP: return "HIP runtime error";
     case VFPI_E_NO_TAPE: return "backward called without a forward tape";
     default: return "unknown error code";

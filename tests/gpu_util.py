@@ -127,10 +127,14 @@ def gpu_step(p, solver=None, tape=False, **opt):
 def fixed_parity(p, ref, L, tol=1e-9, what="", projection="strict", **opt):
     """vfpi_step at a fixed sweep count L against an oracle result ``ref`` of
     the same sweeps: v, lambda and the taped lambda* element by element,
-    each contact's branch, and the branch counts.  Returns (rel_v, rel_lam,
+    each contact's branch, the branch counts, and the residual theta of the
+    last sweep (Alg. 1's reduction: relative bar tol, plus 1e-12 of |v| for
+    the rounding of the last sweep's difference).  Returns (rel_v, rel_lam,
     stats, ties)."""
     v, lam, st, tp = gpu_step(p, tape=True, max_iters=L, fixed_iters=True, projection=projection, **opt)
     assert st["iters"] == L and st["status"] == 1, (what, st)
+    vnorm = float(np.linalg.norm(ref["v"]))
+    assert abs(st["theta"] - ref["theta"]) <= tol * ref["theta"] + 1e-12 * vnorm, (what, st["theta"], ref["theta"])
     ev = gate(v, ref["v"], tol, f"{what} v")
     el = gate(lam, ref["lam"], tol, f"{what} lambda")
     ties = 0
