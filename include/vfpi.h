@@ -153,8 +153,9 @@ typedef struct {
                             default: kind 5 with the fewest chunk slots (2, 4, 5, 6, 8)
                             that fit, else kind 1 with 8 slots and groups of two
                             levels (also with BB step sizes, which take 4 slots).
-                            vfpi_step_backward: 0 or 5 register-resident (S-contacts),
-                            1 streaming, 3 one workgroup.  Batched kinds: see below. */
+                            vfpi_step_backward: 0 or 5 register-resident (S- and
+                            D-contacts), 1 streaming, 3 one workgroup.  Batched
+                            kinds: see below. */
   int32_t cheby_ls;      /* 0: off; l_s >= 1: Chebyshev acceleration (Alg. 3):
                             nu = 1 before sweep l_s, 2/(2 - rho^2) at l_s, then
                             4/(4 - rho^2 nu); rho = min(theta_l / theta_{l-1}, 1) */
