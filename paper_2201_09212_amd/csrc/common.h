@@ -31,12 +31,15 @@ constexpr int kMaxGridSlots = 1024;  // workgroups of a persistent launch (slots
 // lagged one), each slot alone in kSlotPad words (256 bytes) so that the
 // workgroups polling one slot do not contend with those polling its
 // neighbours; region 1 = [2][3][kMaxGridSlots] slots of two words for the
-// three dot products of the Barzilai-Borwein step size.  A slot's value takes
-// two words (see publish in gridsync.h).
+// three dot products of the Barzilai-Borwein step size; region 2 =
+// [2][kMaxGridSlots] tag slots (padded like region 0) for the lagged
+// kernel's D-contact phase.  A slot's value takes two words (see publish in
+// gridsync.h).
 constexpr int kSlotPad = 32;
 constexpr int kSlotRings = 4;
 constexpr int kBBSlotOffset = kSlotRings * kMaxGridSlots * kSlotPad;
-constexpr int kSlotWords = kBBSlotOffset + 12 * kMaxGridSlots;
+constexpr int kDSlotOffset = kBBSlotOffset + 12 * kMaxGridSlots;
+constexpr int kSlotWords = kDSlotOffset + 2 * kMaxGridSlots * kSlotPad;
 
 VFPI_DEV uint64_t ballot(bool p) { return __ballot(p); }
 

@@ -23,6 +23,7 @@ __global__ void k_prep(int32_t n_nodes, int32_t* cmap, int32_t* flags, uint32_t*
     slots[i * kSlotPad + 1] = 0ull;
   }
   for (int64_t i = i0; i < 12 * kMaxGridSlots; i += stride) slots[kBBSlotOffset + i] = 0ull;
+  for (int64_t i = i0; i < 2 * kMaxGridSlots; i += stride) slots[kDSlotOffset + i * kSlotPad] = 0ull;
   if (i0 == 0) {
     flags[0] = 0;
     for (int k = 0; k < kSyncWords; ++k) sync[k] = 0u;
@@ -91,7 +92,8 @@ struct GridArgs {
   const unsigned long long* amax;     // max_d sum_j |a_dj| from the setup
   double* tape_w;                     // nullable: receives the final alpha
   // lagged residual (k_vfpi_regs with LAG): contact results of the last two
-  // sweeps, [2][n_contacts][8] (lambda, lambda*, branch)
+  // sweeps, [2][n_contacts][8] (lambda, lambda*, branch), then (D-contacts)
+  // v* of the two sweep parities, [2][3 n_nodes]
   double* lring;
 };
 
@@ -347,12 +349,14 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_bb(GridArgs a) {
 // wave stores whole cache lines; lambda and the tape are written once, after
 // the last sweep.  Same arithmetic and order as the streaming kernel, except
 // for node-node contacts: their nodes publish v* and read the pair's v* back
-// after a grid barrier (two phases per sweep) instead of recomputing both
-// rows.  BB:
+// after a barrier (two phases per sweep: the whole grid, or with LD the
+// workgroups that share D pairs) instead of recomputing both rows.  BB:
 // Barzilai-Borwein step sizes (W = alpha^l I, see k_vfpi_bb), with the node's
 // own v^{l-1} and A v^{l-1} kept in registers and one more grid reduction
-// (the three dot products) per sweep.
-template <int NW, int KC, int KL, int U, bool COH, bool CH, bool BB = false, bool LAG = false>
+// (the three dot products) per sweep.  LAG: the lagged stop test (below);
+// LD (with LAG): D-contacts, met with their partner workgroups only (without
+// it the lagged form is compiled for S-contacts alone).
+template <int NW, int KC, int KL, int U, bool COH, bool CH, bool BB = false, bool LAG = false, bool LD = false>
 __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   // Registers hold what every sweep streams through the FMA chains: A's first
   // KC levels, the gathered neighbour values and the node's own iterate.  The
@@ -366,14 +370,19 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
   __shared__ double s_out[NW][192];
   __shared__ double s_bw[NW][6][64];      // b (3), W (3)
   __shared__ double s_cr[NW][kPack][64];  // contact record of the lane's node
-  __shared__ double s_lam[NW][6][64];     // lambda, lambda* of the last sweep
+  // lambda, lambda* of the last sweep (LAG: the contact ring holds them)
+  __shared__ double s_lam[LAG ? 1 : NW][6][64];
   __shared__ double s_al[KL > 0 ? NW : 1][KL > 0 ? KL : 1][9][64];
   __shared__ int s_cl[KL > 0 ? NW : 1][KL > 0 ? KL : 1][64];
-  // LAG (S-contacts, no Chebyshev, no BB, more than one workgroup): the stop
-  // test of sweep l is taken after sweep l + 1, and between sweeps a
-  // workgroup waits only for its neighbours (lag_sync in gridsync.h)
+  // LAG (no Chebyshev, no BB, more than one workgroup): the stop test of
+  // sweep l is taken after sweep l + 1, and between sweeps a workgroup waits
+  // only for its neighbours (lag_sync in gridsync.h)
   __shared__ uint32_t s_nbm[LAG ? kMaxGridSlots / 32 : 1];
   __shared__ int s_lflag;
+  // LAG with D-contacts: the workgroups owning the other nodes of this
+  // workgroup's D-contacts (pair_sync in gridsync.h), and whether it has any
+  __shared__ uint32_t s_pbm[LD ? kMaxGridSlots / 32 : 1];
+  __shared__ int s_pflag, s_anyd;
   const int G = gridDim.x;
   const int lb = xcd_logical_block(blockIdx.x, G);
   const int slot = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -453,12 +462,15 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     if (m >= 0)
       for (int e = 0; e < kPack; ++e) s_cr[slot][e][lane] = d.cpack[kPack * (int64_t)m + e];
   }
+  if constexpr (!LAG) {
 #pragma unroll
-  for (int e = 0; e < 6; ++e) s_lam[slot][e][lane] = 0.0;
+    for (int e = 0; e < 6; ++e) s_lam[slot][e][lane] = 0.0;
+  }
   const bool isd = m >= 0 && is_dcontact(d, m);
   const int64_t pi = isd ? d.cpair[2 * (int64_t)m] : -1, pj = isd ? d.cpair[2 * (int64_t)m + 1] : -1;
   const bool owner = !isd || pi == i;  // reports lambda
-  const bool has_d = d.cpair != nullptr;  // the same in every workgroup
+  // the same in every workgroup (the lagged form without LD: S-contacts only)
+  const bool has_d = (!LAG || LD) && d.cpair != nullptr;
   double vp[3] = {vo[0], vo[1], vo[2]};  // v^{l-1} (Chebyshev only; v^0 = v^1)
   int br = BR_OPEN;
   double* vcur = a.v_user;
@@ -473,7 +485,11 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     // neighbour workgroups: the owners of the columns of this workgroup's
     // rows (chunk q belongs to the workgroup lg with lg nch / G <= q, i.e.
     // lg = ((q + 1) G - 1) / nch)
-    for (int k = threadIdx.x; k < kMaxGridSlots / 32; k += blockDim.x) s_nbm[k] = 0u;
+    for (int k = threadIdx.x; k < kMaxGridSlots / 32; k += blockDim.x) {
+      s_nbm[k] = 0u;
+      if constexpr (LD) s_pbm[k] = 0u;
+    }
+    if (threadIdx.x == 0) s_anyd = 0;
     __syncthreads();
     if (act) {
       const int64_t r1 = d.row_ptr[i + 1];
@@ -481,6 +497,12 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         const int64_t q = (int64_t)d.col_idx[k] / 64;
         const int lg = (int)(((q + 1) * G - 1) / nch);
         if (lg != lb) atomicOr(&s_nbm[lg >> 5], 1u << (lg & 31));
+      }
+      if (LD && isd) {
+        const int64_t q = (owner ? pj : pi) / 64;
+        const int lg = (int)(((q + 1) * G - 1) / nch);
+        if (lg != lb) atomicOr(&s_pbm[lg >> 5], 1u << (lg & 31));
+        atomicOr(&s_anyd, 1);
       }
     }
     __syncthreads();
@@ -575,15 +597,23 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         vn[r] = vs[r];
       }
     }
-    if (!LAG && has_d) {
+    bool pair_ok = true;
+    if (has_d) {
       // node-node contacts in two phases: the nodes of D pairs publish v*,
-      // and after a grid barrier both nodes of a pair read the same two
-      // values, so they form the same lambda
+      // and after a barrier (the whole grid; LAG: the partner workgroups,
+      // v* double-buffered by sweep parity behind the lagged contact ring)
+      // both nodes of a pair read the same two values, so they form the same
+      // lambda
+      double* vsb = LAG ? a.lring + 16 * (int64_t)a.n_contacts + (int64_t)(l & 1) * 3 * a.n_nodes : a.avbuf;
       if (act && isd) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) stv<COH>(a.avbuf + 3 * i + r, vs[r]);
+        for (int r = 0; r < 3; ++r) stv<COH>(vsb + 3 * i + r, vs[r]);
       }
-      grid_barrier(a.slots, G, lb, 2 * l - 1, s_poll);
+      if constexpr (LD) {
+        if (s_anyd) pair_ok = pair_sync(a.slots, G, lb, l, s_pbm, &s_pflag);
+      } else if constexpr (!LAG) {
+        grid_barrier(a.slots, G, lb, 2 * l - 1, s_poll);
+      }
       if (act && isd) {
         ContactRec<double> cr;
 #pragma unroll
@@ -594,16 +624,25 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         cr.mu2 = s_cr[slot][12][lane];
         double eta[3], lam[3], ls[3];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) eta[r] = ldv<COH>(a.avbuf + 3 * pi + r) - ldv<COH>(a.avbuf + 3 * pj + r);
+        for (int r = 0; r < 3; ++r) eta[r] = ldv<COH>(vsb + 3 * pi + r) - ldv<COH>(vsb + 3 * pj + r);
         br = contact_solve<double>(cr, eta[0], eta[1], eta[2], d.proj, lam, ls);
         const double sg = owner ? 1.0 : -1.0;  // +W R^T lambda on node i, -W R^T lambda on node j
+        double* rg = (LAG && owner) ? a.lring + ((int64_t)(l & 1) * a.n_contacts + m) * 8 : nullptr;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
           vn[r] = vs[r] + sg * (BB ? alpha : s_bw[slot][3 + r][lane]) * F;
-          s_lam[slot][r][lane] = lam[r];
-          s_lam[slot][3 + r][lane] = ls[r];
+          if constexpr (LAG) {
+            if (owner) {
+              rg[r] = lam[r];
+              rg[3 + r] = ls[r];
+            }
+          } else {
+            s_lam[slot][r][lane] = lam[r];
+            s_lam[slot][3 + r][lane] = ls[r];
+          }
         }
+        if (LAG && owner) rg[6] = (double)br;
       }
     }
     if (act) {
@@ -622,7 +661,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         for (int r = 0; r < 3; ++r) {
           const double F = cr.R[r] * lam[0] + cr.R[3 + r] * lam[1] + cr.R[6 + r] * lam[2];
           vn[r] = vs[r] + (BB ? alpha : s_bw[slot][3 + r][lane]) * F;
-          if (LAG) {
+          if constexpr (LAG) {
             rg[r] = lam[r];
             rg[3 + r] = ls[r];
           } else {
@@ -658,7 +697,8 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
     for (int r = 0; r < 3; ++r) vo[r] = vn[r];
     th2 = block_sum(th2, s_red);
     if constexpr (LAG) {
-      const LagResult lr = lag_sync(a.slots, G, lb, l, th2, a.max_iters, a.fixed, a.tol, s_nbm, s_poll, &s_lflag);
+      LagResult lr = lag_sync(a.slots, G, lb, l, th2, a.max_iters, a.fixed, a.tol, s_nbm, s_poll, &s_lflag);
+      if (!pair_ok) lr = {l, VFPI_S_SYNC_TIMEOUT, (double)INFINITY};
       if (lr.stop == 0) {
         double* t = vcur;
         vcur = vnext;
@@ -686,7 +726,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
           a.v_user[3 * i + r] = vo[r];
           if (a.tape_v) a.tape_v[3 * i + r] = vo[r];
         }
-        if (m >= 0) {
+        if (m >= 0 && owner) {
           const double* rg = a.lring + ((int64_t)(s & 1) * a.n_contacts + m) * 8;
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
@@ -712,6 +752,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       if (CH) ch.observe(theta);
     }
   }
+  if constexpr (LAG) return;  // (the lagged form returns inside the loop)
   int cb[3] = {0, 0, 0};
   if (act && m >= 0 && owner) {
 #pragma unroll
@@ -837,9 +878,10 @@ int64_t regs_grid(int NW, int grid_req, int num_cu, int n_nodes) {
 }
 
 // Register-resident launch (refused with invalid value when the grid does not
-// fit).  KC register levels and KL LDS levels per lane; the rest streamed in
-// groups of U levels.
-template <int NW, int KC, int KL, int U, bool BB>
+// fit).  KC register levels and KL LDS levels per lane (KLL in the lagged
+// form, which keeps no per-lane lambda buffer); the rest streamed in groups
+// of U levels.
+template <int NW, int KC, int KL, int U, bool BB, int KLL = KL>
 hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool sync, hipStream_t st) {
   const int64_t g = regs_grid(NW, grid_req, num_cu, n_nodes);
   if (g < 0) return hipErrorInvalidValue;
@@ -862,11 +904,12 @@ hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
       return hipGetLastError();
     }
     // the lagged residual needs no Chebyshev (nu of sweep l + 1 depends on
-    // theta_l) and S-contacts only (D pairs meet in a grid barrier)
-    const bool lag = !ch && !sync && ga.d.cpair == nullptr;
+    // theta_l); D-contacts take its instance with the partner barrier
+    const bool lag = !ch && !sync;
     kern = ch    ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
-           : lag ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, false, false, true>
-                 : (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>;
+           : !lag ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>
+           : ga.d.cpair ? (const void*)k_vfpi_regs<NW, KC, KLL, U, true, false, false, true, true>
+                        : (const void*)k_vfpi_regs<NW, KC, KLL, U, true, false, false, true>;
   }
   return hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * NW), params, 0, st);
 }
@@ -883,7 +926,7 @@ hipError_t launch_kind5(const Variant& vr, const GridArgs& ga, int num_cu, int N
     return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-           : (vr.nw <= 5) ? launch_regs<5, 6, 3, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 5) ? launch_regs<5, 6, 3, 2, BB, 4>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 6) ? launch_regs<6, 4, 2, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
                           : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
   return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)

@@ -262,6 +262,35 @@ VFPI_DEV LagResult lag_sync(uint64_t* slots, int G, int lb, int l, double th2, i
   return r;
 }
 
+// D-contact phase of sweep l in the lagged kernel: after draining its
+// stores of v* (its D-contact nodes'), a workgroup tags its slot of ring
+// l & 1 and waits for its partner workgroups (the owners of the other nodes
+// of its D-contacts, bitmap pbm in LDS; a symmetric relation) to have tagged
+// theirs.  A ring of two suffices: a workgroup tags its slot for sweep l + 2
+// only after its partners tagged l + 1, which each did after reading what
+// sweep l published.  The v* buffer is double-buffered by the same parity.
+// Bounded: returns false in every thread of the workgroup on a timeout.
+// s_pflag: one int (LDS), for this call only.
+VFPI_DEV bool pair_sync(uint64_t* slots, int G, int lb, int l, const uint32_t* pbm, int* s_pflag) {
+  const unsigned tag = sync_tag(l);
+  uint64_t* ring = slots + kDSlotOffset + (int64_t)(l & 1) * kMaxGridSlots * kSlotPad;
+  // the flag's readers of the previous call have passed the sweep's barriers
+  if (threadIdx.x == 0) *s_pflag = 0;
+  drain();
+  __syncthreads();
+  if (threadIdx.x == 0) st_relaxed<uint64_t>(ring + (int64_t)lb * kSlotPad, (uint64_t)tag);
+  bool ok = true;
+  for (int k = threadIdx.x; k < G && ok; k += blockDim.x) {
+    if ((pbm[k >> 5] >> (k & 31)) & 1u) {
+      uint64_t w0, w1;
+      ok = spin_tag(ring + (int64_t)k * kSlotPad, tag, w0, w1, false);
+    }
+  }
+  if (!ok) atomicOr(s_pflag, 1);
+  __syncthreads();
+  return *s_pflag == 0;
+}
+
 // Plain grid barrier: every write before it is visible to every workgroup
 // after it (through coherent loads).
 VFPI_DEV void grid_barrier(uint64_t* slots, int G, int lb, int seq, double* s_poll) {

@@ -270,14 +270,16 @@ def _step_all(p, **opt):
     return v, lam, st, t
 
 
-@pytest.mark.parametrize("which", ["cloth128", "fem16x16x4", "random700_regs1"])
+@pytest.mark.parametrize("which", ["cloth128", "fem16x16x4", "random700_regs1", "cloth_pair64_d",
+                                   "random700_d_regs1", "random700_d_regs2"])
 def test_lagged_residual_matches_synchronous(which):
     """The register-resident kernel takes the stop test of sweep l after
-    sweep l + 1 and synchronizes each workgroup with its neighbours only; with
-    the sync bit it reduces over the whole grid after every sweep.  Both must
-    stop on the same sweep with the same results, bit for bit: converged at
-    several tolerances, stopped by max_iters (also at 1 and 2 sweeps), and at
-    a fixed sweep count; the converged runs also against the oracle."""
+    sweep l + 1 and synchronizes each workgroup with its neighbours only (and,
+    with D-contacts, with the workgroups that own a contact's partner node);
+    with the sync bit it reduces over the whole grid after every sweep.  Both
+    must stop on the same sweep with the same results, bit for bit: converged
+    at several tolerances, stopped by max_iters (also at 1 and 2 sweeps), and
+    at a fixed sweep count; the converged runs also against the oracle."""
     variant = 0
     if which == "cloth128":
         sc, x, v = scenes.cloth_cfg2(0)
@@ -285,6 +287,11 @@ def test_lagged_residual_matches_synchronous(which):
     elif which == "fem16x16x4":
         sc, x, v = scenes.fem_ctx(0)
         p = sc.assemble(x, v)
+    elif which == "cloth_pair64_d":
+        p = scenes.cloth_pair_collision(0, side=64)
+    elif which.startswith("random700_d"):
+        p = scenes.random_problem(700, 300, 4, degree=5.0, phi_scale=0.5, n_d_contacts=120)
+        variant = 5 | (int(which[-1]) << 8)
     else:
         p = scenes.random_problem(700, 300, 71, degree=5.0, phi_scale=0.5)
         variant = 5 | (1 << 8)
