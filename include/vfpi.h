@@ -266,10 +266,10 @@ int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_contacts* Jc
  * one copy per GPU, held from the first call on that GPU until the process
  * ends.  The call allocates and frees nothing.  The caller still passes every
  * input and output (device pointers, as for vfpi_step); the workspace takes
- *   76 nnzb + 316 N + 112 n_c + 1,671,680 bytes
+ *   84 nnzb + 316 N + 112 n_c + 1,671,680 bytes
  * (each of its 14 parts rounded up to 256 bytes), which must fit the array:
- * about 28,700 nodes of a cloth with 9 blocks per row and a contact on every
- * node (about 31,900 without contacts).  Every call on one GPU
+ * about 26,900 nodes of a cloth with 9 blocks per row and a contact on every
+ * node (about 29,700 without contacts).  Every call on one GPU
  * shares that GPU's array, and each call starts by clearing the parts that
  * must start at zero; two calls that overlap on one GPU (on different
  * streams, or from different threads) race and give undefined results.

@@ -52,7 +52,7 @@ extern "C" int vfpi_create(vfpi_ctx** out, int32_t max_nodes, int32_t max_nnzb, 
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   const size_t n = 3 * (size_t)max_nodes;
   if (e == hipSuccess) e = alloc(&c->scol, (size_t)max_nnzb);
-  if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->sval), 9 * (size_t)max_nnzb);
+  if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->sval), vfpi::kSvalWords64 * (size_t)max_nnzb);
   if (e == hipSuccess) e = alloc(&c->diag, n);
   if (e == hipSuccess) e = alloc(&c->rn2, n);
   if (e == hipSuccess) e = alloc(reinterpret_cast<double**>(&c->w), n);

@@ -87,30 +87,48 @@ VFPI_DEV double dot3<double>(double a0, double a1, double a2, double x0, double 
 // Chunk-interleaved copy of A: the blocks of level k of a chunk (ck of them,
 // one per row that has a k-th block, in lane order) sit at block offset q.
 // Position of entry e (row-major, 0..8) of the block of lane position pos.
-// FP64: entries (0,1), (2,3), (4,5), (6,7) as 16-byte pairs, each pair for
-// all ck lanes in lane order, then entry 8 for all lanes, so that a lane
-// reads its block with four 16-byte loads and one 8-byte load (each load
-// instruction reading one contiguous run over the lanes).  FP32: entry-major
-// (entry e for all lanes, then e + 1).
+// FP64 (80 bytes a block, so every level starts 16-byte aligned): entries
+// (0,1), (2,3), (4,5), (6,7) as 16-byte pairs, each pair for all ck lanes in
+// lane order, then for all lanes a 16-byte record of entry 8 and the block's
+// column (the low 32 bits of the record's second word), so that a lane reads
+// its block and column with five 16-byte loads (each load instruction
+// reading one contiguous run over the lanes).  FP32 (36 bytes a block):
+// entry-major (entry e for all lanes, then e + 1); its columns are in scol.
+constexpr int kSvalWords64 = 10;
 template <class T>
 VFPI_DEV int64_t sval_at(int64_t q, int ck, int pos, int e) {
   if constexpr (sizeof(T) == 8)
-    return 9 * q + (e < 8 ? 2 * (int64_t)ck * (e >> 1) + 2 * pos + (e & 1) : 8 * (int64_t)ck + pos);
+    return kSvalWords64 * q + 2 * ((int64_t)ck * (e >> 1) + pos) + (e & 1);  // e = 8: the record
   else
     return 9 * q + (int64_t)e * ck + pos;
 }
 
-// One block of the interleaved copy into registers (see sval_at).
-VFPI_DEV void load_sblock(const double* __restrict__ sval, int64_t q, int ck, int pos, double a[9]) {
-  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));  // 72 q bytes: 8-byte aligned
-  const double* bp = sval + 9 * q + 2 * pos;
+typedef double vfpi_d2 __attribute__((ext_vector_type(2)));
+
+// Entries 0..7 of a block of the FP64 interleaved copy (see sval_at).
+VFPI_DEV void load_spairs(const double* __restrict__ sval, int64_t q, int ck, int pos, double a[9]) {
+  const double* bp = sval + kSvalWords64 * q + 2 * pos;
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
-    const d2 t = *reinterpret_cast<const d2*>(bp + 2 * (int64_t)ck * p);
+    const vfpi_d2 t = *reinterpret_cast<const vfpi_d2*>(bp + 2 * (int64_t)ck * p);
     a[2 * p] = t.x;
     a[2 * p + 1] = t.y;
   }
-  a[8] = sval[9 * q + 8 * (int64_t)ck + pos];
+}
+// Entry 8 and the column of a block of the FP64 interleaved copy.
+VFPI_DEV int load_srec(const double* __restrict__ sval, int64_t q, int ck, int pos, double& a8) {
+  const vfpi_d2 t = *reinterpret_cast<const vfpi_d2*>(sval + kSvalWords64 * q + 8 * (int64_t)ck + 2 * pos);
+  a8 = t.x;
+  // (through a scalar: this compiler's __builtin_bit_cast of a vector
+  // element reads element 0, whichever element is named)
+  const double cw = t.y;
+  return (int)(uint32_t)__builtin_bit_cast(uint64_t, cw);
+}
+
+// One block of the interleaved copy into registers (see sval_at).
+VFPI_DEV void load_sblock(const double* __restrict__ sval, int64_t q, int ck, int pos, double a[9]) {
+  load_spairs(sval, q, ck, pos, a);
+  a[8] = sval[sval_at<double>(q, ck, pos, 8)];
 }
 VFPI_DEV void load_sblock(const float* __restrict__ sval, int64_t q, int ck, int pos, float a[9]) {
   const float* ap = sval + 9 * q + pos;
@@ -301,6 +319,7 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
       // The group's column indices are issued before its block entries, so
       // that each gather waits only for the columns (loads return in issue
       // order) while the entries are still in flight.
+      // (FP64: each column comes with its block's entry 8, in one load.)
       int c[U], cu[U], pos[U];
       int64_t q[U];
       T a[U][9];
@@ -310,10 +329,18 @@ VFPI_DEV void spmv_rows3_from(const int32_t* __restrict__ scol, const T* __restr
         cu[u] = any ? cnt[u] : cnt[0];
         q[u] = base + (any ? offk[u] : offk[0]);
         pos[u] = min(lanes_below(any ? m[u] : m[0], lane), cu[u] - 1);
-        c[u] = scol[q[u] + pos[u]];
+        if constexpr (sizeof(T) == 8)
+          c[u] = load_srec(sval, q[u], cu[u], pos[u], a[u][8]);
+        else
+          c[u] = scol[q[u] + pos[u]];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) load_sblock(sval, q[u], cu[u], pos[u], a[u]);
+      for (int u = 0; u < U; ++u) {
+        if constexpr (sizeof(T) == 8)
+          load_spairs(sval, q[u], cu[u], pos[u], a[u]);
+        else
+          load_sblock(sval, q[u], cu[u], pos[u], a[u]);
+      }
       T xs[U][3];
 #pragma unroll
       for (int u = 0; u < U; ++u) ldv3<COH>(x, c[u], xs[u]);

@@ -26,7 +26,7 @@ struct vfpi_ctx {
   int num_cu = 0;
   int32_t max_nodes = 0, max_nnzb = 0, max_contacts = 0, max_envs = 0;
   int32_t* scol = nullptr;     // [max_nnzb]   chunk-interleaved column indices
-  void* sval = nullptr;        // [9 max_nnzb] chunk-interleaved values (double or float)
+  void* sval = nullptr;        // [10 max_nnzb] doubles: chunk-interleaved values (FP64: 80 bytes a block, with the column; FP32: 36)
   double* diag = nullptr;      // [3 max_nodes] a_dd
   double* rn2 = nullptr;       // [3 max_nodes] ||A_d*||^2
   void* w = nullptr;           // [3 max_nodes] step sizes

@@ -35,7 +35,7 @@ int64_t carve(unsigned char* base, int32_t N, int32_t nnzb, int32_t nc, vfpi_ctx
   };
   unsigned char* p;
   p = take(4 * (int64_t)nnzb);                         if (c) c->scol = reinterpret_cast<int32_t*>(p);
-  p = take(72 * (int64_t)nnzb);                        if (c) c->sval = p;
+  p = take(80 * (int64_t)nnzb);                        if (c) c->sval = p;
   p = take(8 * n);                                     if (c) c->diag = reinterpret_cast<double*>(p);
   p = take(8 * n);                                     if (c) c->rn2 = reinterpret_cast<double*>(p);
   p = take(8 * n);                                     if (c) c->w = p;

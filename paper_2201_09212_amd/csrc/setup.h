@@ -189,6 +189,9 @@ VFPI_DEV void rows_chunk(int64_t n0, int cnt, int lane, const int32_t* __restric
           sval[sval_at<T>(q, c_, pos, e)] = x[u][e];
           fin &= finite(x[u][e]);
         }
+        // FP64: the column also goes into the block's record, beside entry 8
+        if constexpr (sizeof(T) == 8)
+          sval[sval_at<T>(q, c_, pos, 8) + 1] = __builtin_bit_cast(double, (uint64_t)(uint32_t)c);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
           for (int cc = 0; cc < 3; ++cc) {
