@@ -924,8 +924,8 @@ hipError_t launch_kind5(const Variant& vr, const GridArgs& ga, int num_cu, int N
   const bool kl = vr.lds == 2 || (vr.lds == 0 && long_rows);
   if (kl)
     return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-           : (vr.nw <= 2) ? launch_regs<2, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-           : (vr.nw <= 4) ? launch_regs<4, 9, 4, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 2) ? launch_regs<2, 9, 8, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 4) ? launch_regs<4, 9, 4, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 5) ? launch_regs<5, 6, 3, BB ? 2 : 3, BB, 4, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 6) ? launch_regs<6, 4, 2, BB ? 2 : 3, BB, 3, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
                           : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
