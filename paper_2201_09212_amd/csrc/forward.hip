@@ -530,14 +530,15 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
       Av[1] += dot3(av[k][3], av[k][4], av[k][5], xs[k][0], xs[k][1], xs[k][2]);
       Av[2] += dot3(av[k][6], av[k][7], av[k][8], xs[k][0], xs[k][1], xs[k][2]);
     }
-    // LDS levels, two at a time (both gathers in flight before the products,
-    // unless gathered above); levels a row lacks hold zero blocks, so there
-    // is no branch here
+    // LDS levels: gathered above with the register levels (up to four), or
+    // here all at once (one round trip; gathering two at a time took four);
+    // levels a row lacks hold zero blocks, so there is no branch here
+    constexpr int LG = EL ? 2 : (KL > 0 ? KL : 1);
 #pragma unroll
-    for (int k0 = 0; k0 < KL; k0 += 2) {
-      double xl[2][3];
+    for (int k0 = 0; k0 < KL; k0 += LG) {
+      double xl[LG][3];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < LG; ++u) {
         const int k = k0 + u;
         if (k < KL) {
           if constexpr (EL) {
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(64 * NW) k_vfpi_regs(GridArgs a) {
         }
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < LG; ++u) {
         const int k = k0 + u;
         if (k < KL) {
           // all five LDS reads of the block issue before its products
