@@ -576,7 +576,7 @@ __global__ void __launch_bounds__(64 * NW) k_adjoint_regs(AdjArgs a) {
       out[1] += dot3(av[k][3], av[k][4], av[k][5], xs[k][0], xs[k][1], xs[k][2]);
       out[2] += dot3(av[k][6], av[k][7], av[k][8], xs[k][0], xs[k][1], xs[k][2]);
     }
-    spmv_rows3_from<double, true, (NW >= 8 ? 2 : 1)>(a.scol, a.sval, x, base, nk, lane, KC, off_tail, out);
+    spmv_rows3_from<double, true, 2>(a.scol, a.sval, x, base, nk, lane, KC, off_tail, out);
   };
   // store this wave's node values as whole lines (every thread calls)
   auto publish = [&](double* dst, const double x[3]) {
