@@ -826,15 +826,17 @@ extern "C" int vfpi_step_backward(vfpi_ctx* ctx, const vfpi_bsr* A, const vfpi_c
   if (kind == 0 || kind == 5) {
     const int64_t cap = ctx->num_cu < kMaxGridSlots ? ctx->num_cu : kMaxGridSlots;
     int want_nw = (opts->variant >> 8) & 0xff;
-    for (int nw : {2, 4, 8}) {
+    for (int nw : {2, 4, 5, 8}) {
       if (want_nw && nw < want_nw) continue;
       int64_t g = (nch + nw - 1) / nw;
       if (g > 8 && g % 8 != 0) g += 8 - g % 8;
       if (g > nch) g = nch;
       if (g > cap) continue;
       void* params[] = {&aa};
-      const void* kern = nw == 2 ? (const void*)k_adjoint_regs<2, 9>
-                         : nw == 4 ? (const void*)k_adjoint_regs<4, 9> : (const void*)k_adjoint_regs<8, 4>;
+      const void* kern = nw == 2   ? (const void*)k_adjoint_regs<2, 9>
+                         : nw == 4 ? (const void*)k_adjoint_regs<4, 9>
+                         : nw == 5 ? (const void*)k_adjoint_regs<5, 7>
+                                   : (const void*)k_adjoint_regs<8, 4>;
       vfpi_mark(ctx, 1, stream);
       VFPI_CHECK_HIP(hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * nw), params, 0, stream));
       vfpi_mark(ctx, 2, stream);

@@ -129,6 +129,29 @@ def test_adjoint_grid_and_single_workgroup_agree():
     say(f"  cloth64 adjoint: fwd {a['fwd_stats']['iters']} bwd {a['bwd_stats']['iters']} sweeps, {errs}")
 
 
+def test_adjoint_solid_mesh_launches_agree():
+    """A solid mesh (FEM 16x16x4 cells, rows of up to 19 blocks, so every
+    register-resident instance streams levels beyond the ones it keeps): the
+    register-resident adjoint with 2 (default), 4, 5 and 8 chunk slots and
+    the streaming one agree, and the default matches the oracle's adjoint."""
+    sc, x, v = scenes.fem_ctx(0)
+    p = sc.assemble(x, v)
+    gv = np.random.default_rng(3).normal(size=p.n)
+    a = gpu_fwd_bwd(p, gv, tol=1e-13)
+    assert a["fwd_stats"]["status"] == _abi.VFPI_S_CONVERGED
+    assert a["bwd_stats"]["status"] == _abi.VFPI_S_CONVERGED, a["bwd_stats"]
+    for var in (1, 5 | (4 << 8), 5 | (5 << 8), 5 | (8 << 8)):
+        b = gpu_fwd_bwd(p, gv, tol=1e-13, variant=var)
+        say(f"  FEM adjoint variant {var:#x}: {b['bwd_stats']['iters']} sweeps (default {a['bwd_stats']['iters']})")
+        assert abs(b["bwd_stats"]["iters"] - a["bwd_stats"]["iters"]) <= 1
+        for k in ("b", "A", "phi", "mu"):
+            gate(a[k], b[k], 1e-10, f"FEM variant {var:#x} grad {k}")
+    fwd = oracle.vfpi(p, max_iters=200000, tol=1e-13)
+    ref = oracle_adjoint(p, fwd, gv, tol=1e-14)
+    errs = {k: gate(a[k], ref[k], 1e-6, f"FEM grad {k}") for k in ("b", "A", "phi", "mu")}
+    say(f"  FEM 16x16x4 adjoint: fwd {a['fwd_stats']['iters']} bwd {a['bwd_stats']['iters']} sweeps, {errs}")
+
+
 def test_d_contact_adjoint_launches_agree():
     """D-contacts (two 32x32 cloths meeting, J_m = [R, -R]): the register-
     resident adjoint (default and 8 chunk slots), the streaming one and one
