@@ -950,7 +950,7 @@ def main():
         out["roofline"].update(kernel=rf["kernel"], bytes_per_launch=rf["bytes_per_launch"],
                                dram_gbps=rf["dram_gbps"], measured_copy_gbps=rf["measured_copy_gbps"],
                                dram_frac=(rf["dram_gbps"] / HBM_PEAK_GBPS) if rf["dram_gbps"] else None,
-                               residency="A (68 MB FP64) barely leaves the chip between sweeps: its first ten "
+                               residency="A (68 MB FP64) barely leaves the chip between sweeps: its first eleven "
                                          "block levels stay in VGPRs and LDS, the streamed rest in the 256 MB "
                                          "Infinity Cache; the algorithmic bytes (every block, gather and store "
                                          "once per sweep) are the 8 TB/s roofline's convention, so frac can "

@@ -881,8 +881,10 @@ int64_t regs_grid(int NW, int grid_req, int num_cu, int n_nodes) {
 // Register-resident launch (refused with invalid value when the grid does not
 // fit).  KC register levels and KL LDS levels per lane (KLL in the lagged
 // form, which keeps no per-lane lambda buffer); the rest streamed in groups
-// of U levels (UD in the lagged form with D-contacts).
-template <int NW, int KC, int KL, int U, bool BB, int KLL = KL, int UD = U>
+// of U levels (UD in the lagged form with D-contacts).  The lagged
+// S-contact form, the leanest in registers, takes KCL register levels and
+// groups of UL.
+template <int NW, int KC, int KL, int U, bool BB, int KLL = KL, int UD = U, int KCL = KC, int UL = U>
 hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes, bool sync, hipStream_t st) {
   const int64_t g = regs_grid(NW, grid_req, num_cu, n_nodes);
   if (g < 0) return hipErrorInvalidValue;
@@ -910,7 +912,7 @@ hipError_t launch_regs(const GridArgs& ga, int grid_req, int num_cu, int n_nodes
     kern = ch    ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, true>
            : !lag ? (const void*)k_vfpi_regs<NW, KC, KL, U, true, false>
            : ga.d.cpair ? (const void*)k_vfpi_regs<NW, KC, KLL, UD, true, false, false, true, true>
-                        : (const void*)k_vfpi_regs<NW, KC, KLL, U, true, false, false, true>;
+                        : (const void*)k_vfpi_regs<NW, KCL, KLL, UL, true, false, false, true>;
   }
   return hipLaunchCooperativeKernel(kern, dim3((unsigned)g), dim3(64 * NW), params, 0, st);
 }
@@ -927,7 +929,7 @@ hipError_t launch_kind5(const Variant& vr, const GridArgs& ga, int num_cu, int N
     return (vr.nw <= 1)   ? launch_regs<1, 9, 8, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 2) ? launch_regs<2, 9, 8, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 4) ? launch_regs<4, 9, 4, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-           : (vr.nw <= 5) ? launch_regs<5, 6, 3, BB ? 2 : 3, BB, 4, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+           : (vr.nw <= 5) ? launch_regs<5, 6, 3, BB ? 2 : 3, BB, 4, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
            : (vr.nw <= 6) ? launch_regs<6, 4, 2, BB ? 2 : 3, BB, 3, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
                           : launch_regs<8, 4, 0, 2, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
   return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
