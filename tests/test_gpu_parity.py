@@ -271,7 +271,8 @@ def _step_all(p, **opt):
 
 
 @pytest.mark.parametrize("which", ["cloth128", "fem16x16x4", "fem16x16x4_regs5", "fem16x16x4_regs6",
-                                   "random700_regs1", "cloth_pair64_d", "random700_d_regs1", "random700_d_regs2"])
+                                   "fem16x16x4_regs8", "random700_regs1", "random700_regs5", "random700_regs6",
+                                   "random700_regs8", "cloth_pair64_d", "random700_d_regs1", "random700_d_regs2"])
 def test_lagged_residual_matches_synchronous(which):
     """The register-resident kernel takes the stop test of sweep l after
     sweep l + 1 and synchronizes each workgroup with its neighbours only (and,
@@ -285,9 +286,9 @@ def test_lagged_residual_matches_synchronous(which):
         sc, x, v = scenes.cloth_cfg2(0)
         p = sc.assemble(x, v)
     elif which.startswith("fem16x16x4"):
-        # (with 5 and 6 chunk slots and LDS levels on, the lagged form keeps
-        # one LDS level more than the synchronous one and streams the rest
-        # three levels at a time: the same sums in the same order)
+        # (with 5, 6 and 8 chunk slots the lagged form keeps more levels on
+        # chip than the synchronous one and streams the rest in other groups:
+        # the same sums in the same order)
         sc, x, v = scenes.fem_ctx(0)
         p = sc.assemble(x, v)
         if which != "fem16x16x4":
@@ -299,7 +300,8 @@ def test_lagged_residual_matches_synchronous(which):
         variant = 5 | (int(which[-1]) << 8)
     else:
         p = scenes.random_problem(700, 300, 71, degree=5.0, phi_scale=0.5)
-        variant = 5 | (1 << 8)
+        nw = int(which[len("random700_regs"):])
+        variant = 5 | (nw << 8) | ((1 << 24) if nw > 1 else 0)  # (LDS levels off: the short-row instances)
     sync = variant | (1 << 28)
     cases = [dict(max_iters=5000, tol=t) for t in (1e-3, 1e-5, 1e-8)]
     cases += [dict(max_iters=37, tol=1e-30), dict(max_iters=1, tol=1e-3), dict(max_iters=2, tol=1e-30),
