@@ -935,9 +935,9 @@ hipError_t launch_kind5(const Variant& vr, const GridArgs& ga, int num_cu, int N
   return (vr.nw <= 1)   ? launch_regs<1, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
          : (vr.nw <= 2) ? launch_regs<2, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
          : (vr.nw <= 4) ? launch_regs<4, 9, 0, 1, BB>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-         : (vr.nw <= 5) ? launch_regs<5, 4, 0, 2, BB, 0, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-         : (vr.nw <= 6) ? launch_regs<6, 4, 0, 2, BB, 0, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
-                        : launch_regs<8, 4, 0, 2, BB, 0, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
+         : (vr.nw <= 5) ? launch_regs<5, 6, 0, 2, BB, 0, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+         : (vr.nw <= 6) ? launch_regs<6, 6, 0, 2, BB, 0, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream)
+                        : launch_regs<8, 6, 0, 2, BB, 0, 2, 7, 2>(ga, vr.grid, num_cu, N, vr.sync != 0, stream);
 }
 
 // Barzilai-Borwein step sizes: the register-resident kernel (kind 5) or the
